@@ -1,0 +1,201 @@
+"""Throughput of the collision operator on the 1D DG batch workload (one GPU).
+
+Workload: 192 spatial points (64 elements x 3 Gauss points) of seeded
+two-Maxwellian mixtures with 1% positive noise, N = 32^3 on [-6, 6]^3,
+M = 12 half-sphere points, N_rho = 16, VHS omega = 0.81, gain table truncated
+by SVD at 1e-8.  One step = qcoll_eval + qcoll_conserve over the whole batch.
+The headline value is the FP32 path with the FP64 conservation fix; the FP64
+path is timed beside it, and both are stated with their rel L-inf error
+against the FP64 oracle on sampled items.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-acc]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Q(f,f) evals/sec at N=32^3,M=12,Nρ=16: FP32+fix vs FP64, at rel L∞ err"
+WORKLOAD = "dg1d_32"
+HBM_PEAK_GBS = 8000.0
+
+
+def _oracle_item(args):
+    # CPU baseline worker: the oracle as it stands, one item per call
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    i, f, prm = args
+    from oracle import spectral
+    from oracle import conserve as oc
+    import workloads as W
+    sph = W.sphere_rule(prm["M"])
+    P = spectral.Params(prm["N"], prm["L"], prm["N_rho"], sph[0], sph[1], prm["omega"], svd_tol=prm["svd_tol"])
+    Q = spectral.collide(f, P)
+    Qc, _ = oc.project(Q[None], prm["N"], prm["L"])
+    return i, Qc[0]
+
+
+def cpu_baseline(f, prm, n_items):
+    import multiprocessing as mp
+    cores = min(os.cpu_count() or 1, 16)
+    n = min(n_items, f.shape[0])
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(min(cores, n)) as pool:
+        res = pool.map(_oracle_item, [(i, f[i], prm) for i in range(n)])
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "evals/s", "cores": min(cores, n), "kind": "oracle",
+            "sample": f"{n} of the {f.shape[0]} items (FP64 naive-DFT oracle incl. conservation projection), "
+                      f"{dt:.1f} s wall on {min(cores, n)} processes"}, dict(res)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-acc", action="store_true")
+    ap.add_argument("--cpu-items", type=int, default=0)
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: every item is independent and the box has one GPU; "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1809_10186_amd as qc
+    import workloads as W
+
+    w = W.WORKLOADS[WORKLOAD]
+    N, L, B = w["N"], w["L"], w["items"]
+    sph = W.sphere_rule(w["M"])
+    f_np = W.mixture_for(WORKLOAD)
+    f = torch.from_numpy(f_np).to("cuda")
+    Q = torch.empty_like(f)
+    plans = {}
+    for prec in (qc.QCOLL_FP32, qc.QCOLL_FP64):
+        plans[prec] = qc.Plan(N, L, w["N_rho"], sphere=sph, omega=w["omega"], svd_rank=0,
+                              svd_tol=w["svd_tol"], precision=prec)
+        plans[prec].workspace(B, 0)
+    stream = torch.cuda.current_stream()
+
+    def step(plan):
+        plan.eval(f, Q)
+        plan.conserve(Q)
+
+    def timed(plan, steps, warmup, with_timing):
+        for _ in range(warmup):
+            step(plan)
+        torch.cuda.synchronize()
+        if with_timing:
+            qc.timing_reset()
+            qc.timing_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step(plan)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kt = None
+        if with_timing:
+            qc.timing_enable(False)
+            kt = qc.timing_read()
+        return dt, kt
+
+    dt32, kt32 = timed(plans[qc.QCOLL_FP32], a.steps, a.warmup, True)
+    dt64, kt64 = timed(plans[qc.QCOLL_FP64], a.steps, a.warmup, False)
+    ms32 = dt32 / a.steps * 1e3
+    ms64 = dt64 / a.steps * 1e3
+    del stream
+
+    # roofline of the dominant kernel (largest summed duration) of the FP32 step
+    dom = max(kt32.items(), key=lambda kv: kv[1][0])
+    name, (tot_ms, launches) = dom
+    info = plans[qc.QCOLL_FP32].info()
+    n3 = N ** 3
+    es = 4  # FP32 complex parts
+    Nr, M = w["N_rho"], w["M"]
+    # algorithmic bytes of the whole timed region for the pass-structured hot
+    # loop ("Roofline accounting"):
+    #   gain slab  : per (item, p, q) task, read the spectrum and write one
+    #                complex volume: 2 * 8 B per point (FP32 complex);
+    #   gain pencil: per (item, p) pair, read M complex volumes, write A_p:
+    #                (8 M + 4) B per point.
+    if name == "gain slab":
+        total_bytes = 2 * 2 * es * n3 * B * Nr * M * a.steps
+    elif name == "gain pencil":
+        total_bytes = (2 * es * n3 * M + es * n3) * B * Nr * a.steps
+    else:
+        total_bytes = None
+    avg_ms = tot_ms / launches
+    if total_bytes is not None:
+        bytes_per_launch = total_bytes / launches
+        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        roof = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_ms": round(avg_ms, 4), "launches": launches,
+                "bytes_per_launch": bytes_per_launch}
+    else:
+        roof = {"kernel": name, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": None, "traffic": None, "avg_launch_ms": round(avg_ms, 4), "launches": launches}
+    kernel_ms = {k: round(v[0] / a.steps, 4) for k, v in kt32.items()}
+
+    acc = None
+    cpu = None
+    if not a.no_acc or not a.no_cpu:
+        n_cpu = a.cpu_items or min(2 * (os.cpu_count() or 1), 16)
+        prm = dict(N=N, L=L, N_rho=Nr, M=M, omega=w["omega"], svd_tol=w["svd_tol"])
+        sample = [0, B // 2, B - 1]
+        cpu, ref = cpu_baseline(f_np[:max(n_cpu, 1)], prm, n_cpu) if not a.no_cpu else (None, {})
+        if not a.no_acc:
+            from oracle import spectral
+            from oracle import conserve as oc
+            P = spectral.Params(N, L, Nr, sph[0], sph[1], w["omega"], svd_tol=w["svd_tol"])
+            refs = {}
+            for i in sample:
+                if i in ref:
+                    refs[i] = ref[i]
+                else:
+                    refs[i] = oc.project(spectral.collide(f_np[i], P)[None], N, L)[0][0]
+            acc = {}
+            for prec, tag in ((qc.QCOLL_FP32, "fp32_fix"), (qc.QCOLL_FP64, "fp64")):
+                step(plans[prec])
+                Qh = Q.cpu().numpy()
+                err = max(np.abs(Qh[i] - refs[i]).max() / np.abs(refs[i]).max() for i in sample)
+                acc[tag] = err
+            acc["items"] = sample
+
+    out = {
+        "metric": METRIC,
+        "value": round(B / (ms32 * 1e-3), 1),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms32, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f64 conservation fix)",
+        "data": "synthetic",
+        "config": {"workload": "1D DG batch: 64 elements x 3 Gauss points = 192 points, N=32^3, L=6, "
+                               "M=12, N_rho=16, VHS omega=0.81, SVD rank at 1e-8",
+                   "batch": B, "svd_rank": info["rank"], "step": "qcoll_eval + qcoll_conserve"},
+        "fp64": {"value": round(B / (ms64 * 1e-3), 1), "unit": "evals/s", "ms_per_step": round(ms64, 4)},
+        "rel_linf_err": acc,
+        "roofline": roof,
+        "kernel_ms_per_step": kernel_ms,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * qcoll: batched Boltzmann collision operator Q(f,f) by the fast Fourier
+ * spectral method, for AMD Instinct MI355X (gfx950).
+ *
+ * The method is the one of Jaiswal, Alexeenko and Hu, "A discontinuous
+ * Galerkin fast spectral method for the full Boltzmann equation with general
+ * collision kernels" (Appendix): f on a uniform N^3 velocity grid is
+ * periodised on [-L, L]^3, the kernel modes G(l, m) are separated by a
+ * Gauss-Legendre rule in the relative speed and a half-sphere design in the
+ * scattering direction, and each separated term becomes an FFT convolution.
+ * The library takes the grid values of f and returns the grid values of Q
+ * (Section 3.3: the collision solver is a black box from grid values to grid
+ * values).  The 1/Kn factor of the non-dimensional equation is NOT applied.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Velocity grid: c_j = -L + (j + 1/2) * 2L/N, j = 0..N-1 per axis.  An item
+ *   is a C-order array [N][N][N] of doubles, index (j1, j2, j3) <-> (c1, c2, c3);
+ *   a batch is [batch][N][N][N], contiguous.
+ * - Pointers named f, g, Q, df, out, moments are DEVICE pointers on the device
+ *   the plan was created on, owned by the caller, 8-byte aligned.  Host
+ *   pointers are named as such.  Workspace (ws) is a caller-owned device
+ *   buffer of at least qcoll_workspace_bytes() bytes, 256-byte aligned.
+ * - stream is a hipStream_t (NULL = the default stream).  Every compute entry
+ *   point is asynchronous on that stream; argument errors are detected before
+ *   anything is enqueued and then nothing is enqueued.
+ * - Boundary data are FP64 in both precisions; QCOLL_FP32 computes the
+ *   transforms and products in FP32 and returns FP64.
+ * - Nyquist mode: the DFT index N/2 (frequency -N/2) is shifted as the cosine
+ *   mode of the real trigonometric interpolant, factor cos(pi (N/2) s_d / L)
+ *   per axis, so every intermediate of Q(f,f) is real.
+ * - Errors: a qcoll_status; qcoll_last_error() gives a thread-local detail
+ *   string.  No exception, abort or exit crosses this interface.
+ * - Concurrency: a plan is immutable after creation (except through
+ *   qcoll_plan_set_omega) and may be used from several streams at once if
+ *   each stream has its own workspace.
+ */
+#ifndef QCOLL_H
+#define QCOLL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qcoll_plan_s *qcoll_plan;
+
+typedef enum {
+  QCOLL_OK = 0,
+  QCOLL_EINVAL = 1,     /* invalid argument */
+  QCOLL_ENOTSUP = 2,    /* valid for the method, not supported by this build */
+  QCOLL_ENOMEM = 3,     /* device or host allocation failed */
+  QCOLL_EDEVICE = 4,    /* a HIP call or a kernel launch failed */
+  QCOLL_EWORKSPACE = 5, /* workspace missing or too small */
+  QCOLL_ENONFINITE = 6  /* a non-finite value reached the moment sums */
+} qcoll_status;
+
+typedef enum { QCOLL_FP64 = 0, QCOLL_FP32 = 1 } qcoll_precision;
+
+/* Plan parameters.
+ *   N          points per velocity axis; supported: 8, 12, 16, 24, 32, 48.
+ *   L          half-width of the periodic velocity box [-L, L]^3, L > 0.
+ *   N_rho      Gauss-Legendre nodes of the radial rule on [0, R],
+ *              R = 4L/(3 + sqrt 2) (Appendix: ball truncation); 1..64.
+ *   M          points of the half-sphere rule (Appendix: spherical design).
+ *   sphere     HOST pointer to [M][4] doubles (x, y, z, weight), unit vectors
+ *              with one point per antipodal pair and weights summing to
+ *              2*pi; NULL selects the built-in M = 6 rule (one vertex of each
+ *              antipodal pair of the regular icosahedron, weights 2*pi/6).
+ *   omega      VHS viscosity index, B = b |g|^{2(1-omega)} (Section 2,
+ *              general kernel with alpha = 1); 0.5 <= omega <= 1.
+ *   alpha      VSS scattering exponent; only 1 (VHS) is supported.
+ *   prefactor  kernel constant b; a value <= 0 or NaN selects the
+ *              non-dimensional VHS constant 1/(2^{3-omega} Gamma(2.5-omega) pi)
+ *              (Section 2.1); the BKW case uses 1/(4 pi).
+ *   svd_rank   truncation of the gain-weight table alpha_p(k) = 2 w_p F(k, rho_p)
+ *              (rows p) by its SVD: < 0 keeps the full table exactly (no
+ *              SVD); > 0 keeps that many singular triplets; 0 keeps those
+ *              with sigma_i > svd_tol * sigma_1.
+ *   svd_tol    relative truncation threshold used when svd_rank == 0.
+ *   precision  qcoll_precision.
+ */
+typedef struct {
+  int32_t N;
+  double L;
+  int32_t N_rho;
+  int32_t M;
+  const double *sphere;
+  double omega;
+  double alpha;
+  double prefactor;
+  int32_t svd_rank;
+  double svd_tol;
+  int32_t precision;
+} qcoll_params;
+
+/* Plan facts for diagnostics; filled by qcoll_plan_info. */
+typedef struct {
+  int32_t N, N_rho, M, rank, precision;
+  double L, R, omega, prefactor;
+  double sigma_max, sigma_min_kept; /* singular values of the gain table (0 if no SVD) */
+} qcoll_plan_info_t;
+
+/* Validate parameters without touching any device.  QCOLL_OK, EINVAL or ENOTSUP. */
+qcoll_status qcoll_params_check(const qcoll_params *p);
+
+/* Build a plan on the current HIP device: quadratures, kernel-mode tables
+ * (Appendix, quadrature form of G), per-axis shift tables, optional SVD, all
+ * in FP64 on the host, then copied to device memory owned by the plan.
+ * *out is set only on success. */
+qcoll_status qcoll_plan_create(const qcoll_params *p, qcoll_plan *out);
+
+/* Free the plan and its device tables.  The caller must have synchronised
+ * every stream that used it.  NULL is accepted. */
+qcoll_status qcoll_plan_destroy(qcoll_plan plan);
+
+qcoll_status qcoll_plan_info(qcoll_plan plan, qcoll_plan_info_t *host_out);
+
+/* Copy the radial rule (HOST arrays of N_rho doubles each). */
+qcoll_status qcoll_plan_radial(qcoll_plan plan, double *host_rho, double *host_w);
+
+/* Change omega (and the prefactor if it follows omega) of an untruncated
+ * plan; rebuilds the kernel tables synchronously.  ENOTSUP for truncated plans. */
+qcoll_status qcoll_plan_set_omega(qcoll_plan plan, double omega);
+
+/* Hot-loop schedule: 0 = automatic (fused single-pass kernel where it is
+ * available: FP32 with N <= 32; otherwise two passes over HBM), 1 = force the
+ * two-pass schedule, 2 = require the fused kernel (ENOTSUP where it is not
+ * available).  Results agree to rounding; workspace sizes depend on it. */
+qcoll_status qcoll_plan_set_schedule(qcoll_plan plan, int32_t schedule);
+
+/* Workspace needed by op 0 (qcoll_eval) or 1 (qcoll_vjp) for this batch. */
+size_t qcoll_workspace_bytes(qcoll_plan plan, int64_t batch, int32_t op);
+
+/* Q(f,f) for every item (Appendix):
+ *   Q = sum_p C_p [ sum_q w_q t1_pq t2_pq ] - f * Lam~ f,
+ * t1 = f^N(c + rho_p sigma_q / 2), t2 = f^N(c - rho_p sigma_q / 2) evaluated
+ * spectrally, C_p the Fourier multiplier by alpha_p (or its truncation),
+ * Lam~ the multiplier by the loss weights G(m, m).
+ * f: [batch][N^3] input; Q: [batch][N^3] output (may not alias f).
+ * batch == 0 is a no-op. */
+qcoll_status qcoll_eval(qcoll_plan plan, int64_t batch, const double *f, double *Q,
+                        void *ws, size_t ws_bytes, void *stream);
+
+/* FP64 conservation projection, in place:
+ *   Q <- Q - C^T (C C^T)^{-1} C Q,  rows of C = 1, c1, c2, c3, |c|^2 on the grid,
+ * the nearest grid function (Euclidean) with zero discrete mass, momentum and
+ * energy production.  Not part of the paper's method.
+ * moments: [batch][5] device output of the pre-projection sums
+ * sum_j Q_j phi_i(c_j) dc^3, or NULL.  Non-finite sums raise a device flag
+ * reported by qcoll_poll. */
+qcoll_status qcoll_conserve(qcoll_plan plan, int64_t batch, double *Q, double *moments,
+                            void *stream);
+
+/* Midpoint-rule moments (Section 3.3): out [batch][14] =
+ * n, u1, u2, u3, T, P11, P12, P13, P22, P23, P33, q1, q2, q3 of the
+ * non-dimensional definitions. */
+qcoll_status qcoll_moments(qcoll_plan plan, int64_t batch, const double *f, double *out,
+                           void *stream);
+
+/* Vector-Jacobian product of Q(f,f) with cotangent g:
+ *   df = J_f^T g  ([batch][N^3], may be NULL),
+ *   domega[b] = g_b . dQ(f_b)/d omega ([batch], may be NULL; needs an
+ *   untruncated plan, else ENOTSUP).
+ * through_conserve != 0 differentiates the projected operator (g is first
+ * projected; the projection is symmetric).  Not part of the paper's method. */
+qcoll_status qcoll_vjp(qcoll_plan plan, int64_t batch, const double *f, const double *g,
+                       double *df, double *domega, int32_t through_conserve,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* Per-kernel timing for roofline accounting.  While enabled, every kernel
+ * launch is bracketed by a pair of hipEvents recorded on its own stream, keyed
+ * by the kernel's role name ("gain slab", "gain pencil", ...).  Process-wide;
+ * not thread-safe while enabled.
+ * qcoll_timing_read synchronises the recorded events and returns the summed
+ * duration (ms) and launch count for one name (0 and 0 if never launched);
+ * qcoll_timing_names writes a '\n'-separated list of the names seen into a
+ * HOST buffer of cap bytes (truncated, NUL-terminated). */
+qcoll_status qcoll_timing_enable(int32_t on);
+qcoll_status qcoll_timing_reset(void);
+qcoll_status qcoll_timing_read(const char *name, double *host_ms, int64_t *host_count);
+qcoll_status qcoll_timing_names(char *host_buf, size_t cap);
+
+/* Synchronise the device, then report and clear the non-finite flag. */
+qcoll_status qcoll_poll(qcoll_plan plan);
+
+const char *qcoll_status_str(qcoll_status s);
+const char *qcoll_last_error(void);
+int32_t qcoll_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QCOLL_H */

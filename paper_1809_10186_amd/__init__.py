@@ -1,0 +1,264 @@
+"""Python binding of libqcoll (the fast spectral collision operator on gfx950).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch supplies device memory and the stream.  The library must
+be built in-tree (``python -m paper_1809_10186_amd.build``); importing this
+package without it raises, there is no fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqcoll.so")
+
+QCOLL_FP64, QCOLL_FP32 = 0, 1
+STATUS = {0: "QCOLL_OK", 1: "QCOLL_EINVAL", 2: "QCOLL_ENOTSUP", 3: "QCOLL_ENOMEM",
+          4: "QCOLL_EDEVICE", 5: "QCOLL_EWORKSPACE", 6: "QCOLL_ENONFINITE"}
+
+
+class QcollError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("L", ctypes.c_double), ("N_rho", ctypes.c_int32),
+                ("M", ctypes.c_int32), ("sphere", ctypes.POINTER(ctypes.c_double)),
+                ("omega", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("prefactor", ctypes.c_double), ("svd_rank", ctypes.c_int32),
+                ("svd_tol", ctypes.c_double), ("precision", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("N_rho", ctypes.c_int32), ("M", ctypes.c_int32),
+                ("rank", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("L", ctypes.c_double), ("R", ctypes.c_double), ("omega", ctypes.c_double),
+                ("prefactor", ctypes.c_double), ("sigma_max", ctypes.c_double),
+                ("sigma_min_kept", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libqcoll.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1809_10186_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+        sig = {
+            "qcoll_params_check": ([ctypes.POINTER(Params)], i32),
+            "qcoll_plan_create": ([ctypes.POINTER(Params), ctypes.POINTER(vp)], i32),
+            "qcoll_plan_destroy": ([vp], i32),
+            "qcoll_plan_info": ([vp, ctypes.POINTER(PlanInfo)], i32),
+            "qcoll_plan_radial": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], i32),
+            "qcoll_plan_set_omega": ([vp, ctypes.c_double], i32),
+            "qcoll_plan_set_schedule": ([vp, i32], i32),
+            "qcoll_workspace_bytes": ([vp, i64, i32], ctypes.c_size_t),
+            "qcoll_eval": ([vp, i64, dp, dp, vp, ctypes.c_size_t, vp], i32),
+            "qcoll_conserve": ([vp, i64, dp, dp, vp], i32),
+            "qcoll_moments": ([vp, i64, dp, dp, vp], i32),
+            "qcoll_vjp": ([vp, i64, dp, dp, dp, dp, i32, vp, ctypes.c_size_t, vp], i32),
+            "qcoll_poll": ([vp], i32),
+            "qcoll_status_str": ([i32], ctypes.c_char_p),
+            "qcoll_last_error": ([], ctypes.c_char_p),
+            "qcoll_version": ([], i32),
+            "qcoll_timing_enable": ([i32], i32),
+            "qcoll_timing_reset": ([], i32),
+            "qcoll_timing_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_int64)], i32),
+            "qcoll_timing_names": ([ctypes.c_char_p, ctypes.c_size_t], i32),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != 0:
+        raise QcollError(code, lib().qcoll_last_error().decode())
+
+
+def make_params(N, L, N_rho, sphere=None, omega=1.0, prefactor=None, svd_rank=-1, svd_tol=0.0,
+                precision=QCOLL_FP64, alpha=1.0):
+    """Build a Params struct; sphere is (points [M,3], weights [M]) or None for the built-in M=6 rule.
+    Returns (params, keepalive)."""
+    keep = None
+    p = Params()
+    p.N, p.L, p.N_rho = int(N), float(L), int(N_rho)
+    if sphere is None:
+        p.M = 6
+        p.sphere = None
+    else:
+        pts, w = sphere
+        M = len(w)
+        arr = (ctypes.c_double * (4 * M))()
+        for q in range(M):
+            arr[4 * q:4 * q + 3] = [float(x) for x in pts[q]]
+            arr[4 * q + 3] = float(w[q])
+        keep = arr
+        p.M = M
+        p.sphere = ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
+    p.omega = float(omega)
+    p.alpha = float(alpha)
+    p.prefactor = float("nan") if prefactor is None else float(prefactor)
+    p.svd_rank = int(svd_rank)
+    p.svd_tol = float(svd_tol)
+    p.precision = int(precision)
+    return p, keep
+
+
+def params_check(**kw):
+    p, keep = make_params(**kw)
+    code = lib().qcoll_params_check(ctypes.byref(p))
+    del keep
+    return code, lib().qcoll_last_error().decode()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A plan for one velocity grid and kernel.  See include/qcoll.h."""
+
+    def __init__(self, N, L, N_rho, sphere=None, omega=1.0, prefactor=None, svd_rank=-1,
+                 svd_tol=0.0, precision=QCOLL_FP64, device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("qcoll needs a ROCm GPU")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        p, keep = make_params(N, L, N_rho, sphere, omega, prefactor, svd_rank, svd_tol, precision)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().qcoll_plan_create(ctypes.byref(p), ctypes.byref(h)))
+        del keep
+        self._h = h
+        self.N, self.L, self.N_rho = int(N), float(L), int(N_rho)
+        self.precision = precision
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            import torch
+            torch.cuda.synchronize(self.device)
+            lib().qcoll_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        i = PlanInfo()
+        _check(lib().qcoll_plan_info(self._h, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in PlanInfo._fields_}
+
+    def radial(self):
+        n = self.N_rho
+        r = (ctypes.c_double * n)()
+        w = (ctypes.c_double * n)()
+        _check(lib().qcoll_plan_radial(self._h, r, w))
+        return list(r), list(w)
+
+    def set_omega(self, omega):
+        _check(lib().qcoll_plan_set_omega(self._h, float(omega)))
+
+    def set_schedule(self, schedule):
+        """0 auto, 1 two-pass, 2 fused (see include/qcoll.h)."""
+        _check(lib().qcoll_plan_set_schedule(self._h, int(schedule)))
+        self._ws = None
+
+    def workspace_bytes(self, batch, op=0):
+        return int(lib().qcoll_workspace_bytes(self._h, int(batch), int(op)))
+
+    def workspace(self, batch, op=0):
+        import torch
+        need = self.workspace_bytes(batch, op)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def _check_f(self, t, name):
+        import torch
+        n = self.N
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.device != self.device:
+            raise ValueError(f"{name} must be a contiguous float64 tensor on {self.device}")
+        if t.shape[-3:] != (n, n, n):
+            raise ValueError(f"{name} must have trailing shape ({n}, {n}, {n})")
+        return t.reshape(-1, n, n, n).shape[0]
+
+    def eval(self, f, out=None, stream=None):
+        import torch
+        batch = self._check_f(f, "f")
+        if out is None:
+            out = torch.empty_like(f)
+        ws = self.workspace(batch, 0)
+        _check(lib().qcoll_eval(self._h, batch, _ptr(f), _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+        return out
+
+    def conserve(self, Q, moments=None, stream=None):
+        batch = self._check_f(Q, "Q")
+        _check(lib().qcoll_conserve(self._h, batch, _ptr(Q), _ptr(moments), _stream(stream)))
+        return Q
+
+    def moments(self, f, out=None, stream=None):
+        import torch
+        batch = self._check_f(f, "f")
+        if out is None:
+            out = torch.empty(f.shape[:-3] + (14,), dtype=torch.float64, device=self.device)
+        _check(lib().qcoll_moments(self._h, batch, _ptr(f), _ptr(out), _stream(stream)))
+        return out
+
+    def vjp(self, f, g, df=None, domega=None, through_conserve=False, want_df=True, want_domega=False,
+            stream=None):
+        import torch
+        batch = self._check_f(f, "f")
+        self._check_f(g, "g")
+        if want_df and df is None:
+            df = torch.empty_like(f)
+        if want_domega and domega is None:
+            domega = torch.empty(batch, dtype=torch.float64, device=self.device)
+        ws = self.workspace(batch, 1)
+        _check(lib().qcoll_vjp(self._h, batch, _ptr(f), _ptr(g), _ptr(df if want_df else None),
+                               _ptr(domega if want_domega else None), int(bool(through_conserve)),
+                               _ptr(ws), ws.numel(), _stream(stream)))
+        return df, domega
+
+    def poll(self):
+        _check(lib().qcoll_poll(self._h))
+
+
+
+def timing_enable(on=True):
+    _check(lib().qcoll_timing_enable(int(bool(on))))
+
+
+def timing_reset():
+    _check(lib().qcoll_timing_reset())
+
+
+def timing_read():
+    """{kernel role: (total_ms, launches)} for every role launched since the last reset."""
+    buf = ctypes.create_string_buffer(4096)
+    _check(lib().qcoll_timing_names(buf, 4096))
+    out = {}
+    for name in filter(None, buf.value.decode().split("\n")):
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().qcoll_timing_read(name.encode(), ctypes.byref(ms), ctypes.byref(n)))
+        out[name] = (ms.value, n.value)
+    return out

@@ -1,0 +1,234 @@
+// C ABI: argument validation, plan lifetime and dispatch.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "qcoll_internal.h"
+
+struct qcoll_plan_s {
+  qcoll::Plan p;
+};
+
+namespace qcoll {
+qcoll_status plan_build(Plan &p, const qcoll_params &prm);
+qcoll_status plan_set_omega(Plan &p, double omega);
+void plan_free(Plan &p);
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+}  // namespace qcoll
+
+using qcoll::set_error;
+
+namespace {
+
+qcoll_status fail(qcoll_status s, const std::string &msg) {
+  set_error(msg);
+  return s;
+}
+
+qcoll_status check_device(const qcoll::Plan &p) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(QCOLL_EDEVICE, "hipGetDevice failed");
+  if (dev != p.device) return fail(QCOLL_EINVAL, "current device differs from the plan's device");
+  return QCOLL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t qcoll_version(void) { return 1; }
+
+const char *qcoll_status_str(qcoll_status s) {
+  switch (s) {
+    case QCOLL_OK: return "QCOLL_OK";
+    case QCOLL_EINVAL: return "QCOLL_EINVAL";
+    case QCOLL_ENOTSUP: return "QCOLL_ENOTSUP";
+    case QCOLL_ENOMEM: return "QCOLL_ENOMEM";
+    case QCOLL_EDEVICE: return "QCOLL_EDEVICE";
+    case QCOLL_EWORKSPACE: return "QCOLL_EWORKSPACE";
+    case QCOLL_ENONFINITE: return "QCOLL_ENONFINITE";
+  }
+  return "QCOLL_<unknown>";
+}
+
+const char *qcoll_last_error(void) { return qcoll::g_err.c_str(); }
+
+qcoll_status qcoll_params_check(const qcoll_params *p) {
+  if (!p) return fail(QCOLL_EINVAL, "params is NULL");
+  if (!(p->N > 0) || p->N % 2) return fail(QCOLL_EINVAL, "N must be a positive even integer");
+  if (!qcoll::supported_N(p->N)) return fail(QCOLL_ENOTSUP, "N must be one of 8, 12, 16, 24, 32, 48");
+  if (!(p->L > 0.0) || !std::isfinite(p->L)) return fail(QCOLL_EINVAL, "L must be finite and > 0");
+  if (p->N_rho < 1) return fail(QCOLL_EINVAL, "N_rho must be >= 1");
+  if (p->N_rho > 64) return fail(QCOLL_ENOTSUP, "N_rho must be <= 64");
+  if (!(p->omega >= 0.5 && p->omega <= 1.0)) return fail(QCOLL_EINVAL, "omega must lie in [0.5, 1]");
+  if (!(p->alpha == 1.0)) {
+    if (p->alpha > 1.0 && p->alpha <= 2.0)
+      return fail(QCOLL_ENOTSUP, "VSS kernels (alpha in (1, 2]) are not supported; alpha must be 1");
+    return fail(QCOLL_EINVAL, "alpha must be 1 (VHS)");
+  }
+  if (std::isinf(p->prefactor)) return fail(QCOLL_EINVAL, "prefactor must be finite (or NaN/<= 0 for the VHS constant)");
+  if (p->precision != QCOLL_FP64 && p->precision != QCOLL_FP32) return fail(QCOLL_EINVAL, "unknown precision");
+  if (p->svd_rank == 0 && !(p->svd_tol > 0.0 && p->svd_tol < 1.0))
+    return fail(QCOLL_EINVAL, "svd_rank == 0 needs 0 < svd_tol < 1");
+  if (p->svd_rank > p->N_rho) return fail(QCOLL_EINVAL, "svd_rank must be <= N_rho");
+  if (p->sphere) {
+    if (p->M < 1 || p->M > 256) return fail(QCOLL_EINVAL, "M must be in 1..256");
+    double wsum = 0.0;
+    for (int q = 0; q < p->M; ++q) {
+      const double *s = p->sphere + 4 * q;
+      const double n = std::sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+      if (!(std::fabs(n - 1.0) < 1e-12)) return fail(QCOLL_EINVAL, "sphere points must be unit vectors");
+      if (!(s[3] > 0.0)) return fail(QCOLL_EINVAL, "sphere weights must be > 0");
+      wsum += s[3];
+    }
+    if (!(std::fabs(wsum - 2.0 * M_PI) < 1e-10))
+      return fail(QCOLL_EINVAL, "half-sphere weights must sum to 2*pi");
+  } else if (!(p->M == 6 || p->M == 0)) {
+    return fail(QCOLL_EINVAL, "sphere is NULL: only the built-in M = 6 rule is available");
+  }
+  return QCOLL_OK;
+}
+
+qcoll_status qcoll_plan_create(const qcoll_params *prm, qcoll_plan *out) {
+  if (!out) return fail(QCOLL_EINVAL, "out is NULL");
+  qcoll_status st = qcoll_params_check(prm);
+  if (st != QCOLL_OK) return st;
+  auto *h = new (std::nothrow) qcoll_plan_s;
+  if (!h) return fail(QCOLL_ENOMEM, "host allocation failed");
+  st = qcoll::plan_build(h->p, *prm);
+  if (st != QCOLL_OK) {
+    qcoll::plan_free(h->p);
+    delete h;
+    return st;
+  }
+  *out = h;
+  return QCOLL_OK;
+}
+
+qcoll_status qcoll_plan_destroy(qcoll_plan plan) {
+  if (!plan) return QCOLL_OK;
+  qcoll::plan_free(plan->p);
+  delete plan;
+  return QCOLL_OK;
+}
+
+qcoll_status qcoll_plan_info(qcoll_plan plan, qcoll_plan_info_t *o) {
+  if (!plan || !o) return fail(QCOLL_EINVAL, "NULL argument");
+  const auto &p = plan->p;
+  o->N = p.N;
+  o->N_rho = p.N_rho;
+  o->M = p.M;
+  o->rank = p.rank;
+  o->precision = p.precision;
+  o->L = p.L;
+  o->R = p.R;
+  o->omega = p.omega;
+  o->prefactor = p.b;
+  o->sigma_max = p.sigma_max;
+  o->sigma_min_kept = p.sigma_min_kept;
+  return QCOLL_OK;
+}
+
+qcoll_status qcoll_plan_radial(qcoll_plan plan, double *rho, double *w) {
+  if (!plan || !rho || !w) return fail(QCOLL_EINVAL, "NULL argument");
+  for (int i = 0; i < plan->p.N_rho; ++i) {
+    rho[i] = plan->p.rho[i];
+    w[i] = plan->p.w_rho[i];
+  }
+  return QCOLL_OK;
+}
+
+qcoll_status qcoll_plan_set_omega(qcoll_plan plan, double omega) {
+  if (!plan) return fail(QCOLL_EINVAL, "plan is NULL");
+  if (!(omega >= 0.5 && omega <= 1.0)) return fail(QCOLL_EINVAL, "omega must lie in [0.5, 1]");
+  qcoll_status st = check_device(plan->p);
+  if (st != QCOLL_OK) return st;
+  return qcoll::plan_set_omega(plan->p, omega);
+}
+
+qcoll_status qcoll_plan_set_schedule(qcoll_plan plan, int32_t schedule) {
+  if (!plan) return fail(QCOLL_EINVAL, "plan is NULL");
+  if (schedule < 0 || schedule > 2) return fail(QCOLL_EINVAL, "schedule must be 0, 1 or 2");
+  if (schedule == 2 && !qcoll::fused_gain_supported(plan->p.N, plan->p.precision))
+    return fail(QCOLL_ENOTSUP, "the fused gain kernel needs FP32 and N <= 32");
+  plan->p.schedule = schedule;
+  return QCOLL_OK;
+}
+
+size_t qcoll_workspace_bytes(qcoll_plan plan, int64_t batch, int32_t op) {
+  if (!plan || batch < 0 || (op != 0 && op != 1)) return 0;
+  return qcoll::make_layout(plan->p, batch, op).total;
+}
+
+qcoll_status qcoll_eval(qcoll_plan plan, int64_t batch, const double *f, double *Q, void *ws, size_t ws_bytes,
+                        void *stream) {
+  if (!plan) return fail(QCOLL_EINVAL, "plan is NULL");
+  if (batch < 0) return fail(QCOLL_EINVAL, "batch must be >= 0");
+  if (batch == 0) return QCOLL_OK;
+  if (!f || !Q) return fail(QCOLL_EINVAL, "f and Q must be non-NULL");
+  const long n3 = plan->p.n3();
+  if ((const void *)f < (const void *)(Q + batch * n3) && (const void *)Q < (const void *)(f + batch * n3))
+    return fail(QCOLL_EINVAL, "Q must not overlap f");
+  const qcoll::Layout lay = qcoll::make_layout(plan->p, batch, 0);
+  if (!ws || ws_bytes < lay.total) return fail(QCOLL_EWORKSPACE, "workspace missing or smaller than qcoll_workspace_bytes");
+  qcoll_status st = check_device(plan->p);
+  if (st != QCOLL_OK) return st;
+  return qcoll::launch_eval(plan->p, batch, f, Q, ws, lay, static_cast<hipStream_t>(stream));
+}
+
+qcoll_status qcoll_conserve(qcoll_plan plan, int64_t batch, double *Q, double *moments, void *stream) {
+  if (!plan) return fail(QCOLL_EINVAL, "plan is NULL");
+  if (batch < 0) return fail(QCOLL_EINVAL, "batch must be >= 0");
+  if (batch == 0) return QCOLL_OK;
+  if (!Q) return fail(QCOLL_EINVAL, "Q must be non-NULL");
+  if (batch > 0x7fffffff) return fail(QCOLL_EINVAL, "batch too large");
+  qcoll_status st = check_device(plan->p);
+  if (st != QCOLL_OK) return st;
+  return qcoll::launch_conserve(plan->p, batch, Q, moments, static_cast<hipStream_t>(stream));
+}
+
+qcoll_status qcoll_moments(qcoll_plan plan, int64_t batch, const double *f, double *out, void *stream) {
+  if (!plan) return fail(QCOLL_EINVAL, "plan is NULL");
+  if (batch < 0) return fail(QCOLL_EINVAL, "batch must be >= 0");
+  if (batch == 0) return QCOLL_OK;
+  if (!f || !out) return fail(QCOLL_EINVAL, "f and out must be non-NULL");
+  if (batch > 0x7fffffff) return fail(QCOLL_EINVAL, "batch too large");
+  qcoll_status st = check_device(plan->p);
+  if (st != QCOLL_OK) return st;
+  return qcoll::launch_moments(plan->p, batch, f, out, static_cast<hipStream_t>(stream));
+}
+
+qcoll_status qcoll_vjp(qcoll_plan plan, int64_t batch, const double *f, const double *g, double *df,
+                       double *domega, int32_t through_conserve, void *ws, size_t ws_bytes, void *stream) {
+  if (!plan) return fail(QCOLL_EINVAL, "plan is NULL");
+  if (batch < 0) return fail(QCOLL_EINVAL, "batch must be >= 0");
+  if (batch == 0) return QCOLL_OK;
+  if (!f || !g) return fail(QCOLL_EINVAL, "f and g must be non-NULL");
+  if (!df && !domega) return QCOLL_OK;
+  if (domega && plan->p.truncated)
+    return fail(QCOLL_ENOTSUP, "the omega gradient needs an untruncated plan (svd_rank < 0)");
+  const qcoll::Layout lay = qcoll::make_layout(plan->p, batch, 1);
+  if (!ws || ws_bytes < lay.total) return fail(QCOLL_EWORKSPACE, "workspace missing or smaller than qcoll_workspace_bytes");
+  qcoll_status st = check_device(plan->p);
+  if (st != QCOLL_OK) return st;
+  (void)through_conserve;
+  return fail(QCOLL_ENOTSUP, "qcoll_vjp is not available in this build");
+}
+
+qcoll_status qcoll_poll(qcoll_plan plan) {
+  if (!plan) return fail(QCOLL_EINVAL, "plan is NULL");
+  if (hipDeviceSynchronize() != hipSuccess) return fail(QCOLL_EDEVICE, "hipDeviceSynchronize failed");
+  int h = 0;
+  if (hipMemcpy(&h, plan->p.flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(QCOLL_EDEVICE, "hipMemcpy failed");
+  if (h) {
+    hipMemset(plan->p.flag, 0, sizeof(int));
+    return fail(QCOLL_ENONFINITE, "a non-finite value reached the moment sums");
+  }
+  return QCOLL_OK;
+}
+
+}  // extern "C"

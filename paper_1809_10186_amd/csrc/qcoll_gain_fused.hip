@@ -1,0 +1,181 @@
+// Fused gain kernel (FP32, N <= 32): the whole hot loop of one (item, radial
+// node) pair in one workgroup, with no intermediate volume in HBM.
+//
+// For each half-sphere point q the kernel forms u = ifft3[c_s * H] with the
+// real shift multiplier c_s = Re beta_s + Im beta_s (s = rho_p sigma_q / 2) and
+// accumulates A_p += w_q (Re(u)^2 - Im(u)^2) = w_q t1 t2 (Appendix, the
+// product of the two shifted copies of f for one quadrature term).
+//
+// Layout: the workgroup has N^2 lanes, one pencil each.
+//   stage A  lane (k2, k3): pencil along axis 1, loaded straight from H with
+//            the multiplier applied (coalesced: consecutive lanes read
+//            consecutive addresses), inverse FFT in registers -> index j1;
+//   stage B  lane (j1, k3): pencil along axis 2 after an LDS transpose;
+//   stage C  lane (j1, j2): pencil along axis 3 after a second transpose;
+//            the lane owns A_p[j1][j2][:] in registers across all q.
+// Each transpose moves the real parts, then the imaginary parts, through one
+// LDS tile of N * (N^2 + 32) floats (135 KiB at N = 32).  The padding makes
+// both the writes and the reads of each transpose free of bank conflicts at
+// N = 32.  Workgroups are renumbered so that consecutive (item, node) pairs
+// run on the same XCD and share the item's spectrum in that XCD's L2.
+#include <hip/hip_runtime.h>
+
+#include "qcoll_fft.hpp"
+#include "qcoll_internal.h"
+
+namespace qcoll {
+
+template <int N>
+struct FusedGeom {
+  // pencils per lane: two at N = 32 so that the 2 x 32 complex values plus the
+  // 2 x 32 accumulators of a lane fit the 256-VGPR budget of 512-lane groups
+  static constexpr int PPL = (N == 32) ? 2 : 1;
+  static constexpr int NL = N * N / PPL;
+  static constexpr int S1 = N * N + 32;
+  static constexpr size_t lds_bytes = size_t(N) * S1 * sizeof(float);
+};
+
+// move one component (re or im) of every pencil of the lane through LDS
+template <int N, int PPL, class WA, class RA>
+__device__ __forceinline__ void lds_transpose(float *lds, float (*v)[N], WA wa, RA ra) {
+  static_for<0, PPL>([&](auto u) {
+    static_for<0, N>([&](auto i) {
+      lds[wa(decltype(u)::value, decltype(i)::value)] = v[decltype(u)::value][decltype(i)::value];
+    });
+  });
+  __syncthreads();
+  static_for<0, PPL>([&](auto u) {
+    static_for<0, N>([&](auto i) {
+      v[decltype(u)::value][decltype(i)::value] = lds[ra(decltype(u)::value, decltype(i)::value)];
+    });
+  });
+  __syncthreads();
+}
+
+template <int N>
+__global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<float> *__restrict__ H,
+                                                                 const cplx<float> *__restrict__ phase,
+                                                                 const float *__restrict__ wq,
+                                                                 float *__restrict__ A, long nbp, int M, int Nr,
+                                                                 float scale) {
+  using G = FusedGeom<N>;
+  constexpr int PPL = G::PPL, NL = G::NL;
+  constexpr long n2 = long(N) * N, n3 = n2 * N;
+  constexpr int S1 = G::S1;
+  extern __shared__ float lds[];
+
+  // XCD-aware renumbering: block i runs on XCD i % 8; give each XCD a
+  // contiguous range of logical pair indices.
+  const long nb = gridDim.x;
+  const long full = nb / 8, rem = nb % 8;
+  const long x = blockIdx.x % 8;
+  const long bp = x * full + (x < rem ? x : rem) + blockIdx.x / 8;
+  if (bp >= nbp) return;  // uniform per workgroup
+  const long b = bp / Nr;
+  const int p = int(bp % Nr);
+
+  // pencil u of this lane is t = lane + u*NL, split as (hi, lo) = (t / N, t % N)
+  const int lane = threadIdx.x;
+  int hi[PPL], lo[PPL];
+  static_for<0, PPL>([&](auto u) {
+    const int t = lane + decltype(u)::value * NL;
+    hi[decltype(u)::value] = t / N;
+    lo[decltype(u)::value] = t % N;
+  });
+
+  float acc[PPL][N];
+  static_for<0, PPL>([&](auto u) {
+    static_for<0, N>([&](auto j) { acc[decltype(u)::value][decltype(j)::value] = 0.f; });
+  });
+
+  const cplx<float> *h = H + b * n3 + lane;
+  for (int q = 0; q < M; ++q) {
+    const cplx<float> *ph = phase + size_t(p * M + q) * 3 * N;
+    float zr[PPL][N], zi[PPL][N];
+    // stage A: lane (k2, k3) = (hi, lo); c(k1) = Re(b1 b23) + Im(b1 b23)
+    static_for<0, PPL>([&](auto uu) {
+      constexpr int u = decltype(uu)::value;
+      const cplx<float> b2 = ph[N + hi[u]], b3 = ph[2 * N + lo[u]];
+      const float xr = b2.re * b3.re - b2.im * b3.im;
+      const float yi = b2.re * b3.im + b2.im * b3.re;
+      const float P = (xr + yi) * scale, Qm = (xr - yi) * scale;
+      static_for<0, N>([&](auto k) {
+        constexpr int kk = decltype(k)::value;
+        const cplx<float> v = h[kk * n2 + u * NL];
+        const cplx<float> b1 = ph[kk];
+        const float c = b1.re * P + b1.im * Qm;
+        zr[u][kk] = v.re * c;
+        zi[u][kk] = v.im * c;
+      });
+      fft_reg<N, +1, float>(zr[u], zi[u]);
+    });
+    // A -> B: element (j1, k2, k3) at j1*S1 + k2*N + k3
+    auto wa1 = [&](int u, int i) { return i * S1 + hi[u] * N + lo[u]; };
+    auto ra1 = [&](int u, int i) { return hi[u] * S1 + i * N + lo[u]; };
+    lds_transpose<N, PPL>(lds, zr, wa1, ra1);
+    lds_transpose<N, PPL>(lds, zi, wa1, ra1);
+    static_for<0, PPL>([&](auto u) { fft_reg<N, +1, float>(zr[decltype(u)::value], zi[decltype(u)::value]); });
+    // B -> C: element (j1, j2, k3) at j1*S1 + k3*(N+1) + j2
+    auto wa2 = [&](int u, int i) { return hi[u] * S1 + lo[u] * (N + 1) + i; };
+    auto ra2 = [&](int u, int i) { return hi[u] * S1 + i * (N + 1) + lo[u]; };
+    lds_transpose<N, PPL>(lds, zr, wa2, ra2);
+    lds_transpose<N, PPL>(lds, zi, wa2, ra2);
+    const float w = wq[q];
+    static_for<0, PPL>([&](auto uu) {
+      constexpr int u = decltype(uu)::value;
+      fft_reg<N, +1, float>(zr[u], zi[u]);
+      static_for<0, N>([&](auto j) {
+        constexpr int jj = decltype(j)::value;
+        acc[u][jj] += w * (zr[u][jj] * zr[u][jj] - zi[u][jj] * zi[u][jj]);
+      });
+    });
+  }
+  // lane (j1, j2) owns the row A_p[j1][j2][:]
+  static_for<0, PPL>([&](auto uu) {
+    constexpr int u = decltype(uu)::value;
+    float *a = A + bp * n3 + long(lane + u * NL) * N;
+    static_for<0, N>([&](auto j) { a[decltype(j)::value] = acc[u][decltype(j)::value]; });
+  });
+}
+
+template <int N>
+static qcoll_status launch_fused(const Plan &p, const cplx<float> *H, float *A, long nbp, hipStream_t st) {
+  using G = FusedGeom<N>;
+  // the LDS tile exceeds the default dynamic limit at N = 32; set per call
+  // (cheap) so that every device the process uses gets the attribute
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_gain_fused<N>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, int(G::lds_bytes)) != hipSuccess) {
+    set_error("hipFuncSetAttribute failed for the fused gain kernel");
+    return QCOLL_EDEVICE;
+  }
+  TimedLaunch tl("gain fused", st);
+  const float scale = float(1.0 / double(long(N) * N * N));
+  hipLaunchKernelGGL(k_gain_fused<N>, dim3(unsigned(nbp)), dim3(G::NL), G::lds_bytes, st, H,
+                     reinterpret_cast<const cplx<float> *>(p.phase), reinterpret_cast<const float *>(p.wq), A,
+                     nbp, p.M, p.N_rho, scale);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error(std::string("gain fused: ") + hipGetErrorString(e));
+    return QCOLL_EDEVICE;
+  }
+  return QCOLL_OK;
+}
+
+bool fused_gain_supported(int N, int precision) {
+  return precision == QCOLL_FP32 && (N == 8 || N == 12 || N == 16 || N == 24 || N == 32);
+}
+
+qcoll_status launch_gain_fused(const Plan &p, const void *H, void *A, long nbp, hipStream_t st) {
+  const auto *h = static_cast<const cplx<float> *>(H);
+  auto *a = static_cast<float *>(A);
+  switch (p.N) {
+    case 8: return launch_fused<8>(p, h, a, nbp, st);
+    case 12: return launch_fused<12>(p, h, a, nbp, st);
+    case 16: return launch_fused<16>(p, h, a, nbp, st);
+    case 24: return launch_fused<24>(p, h, a, nbp, st);
+    case 32: return launch_fused<32>(p, h, a, nbp, st);
+    default: set_error("fused gain kernel: unsupported N"); return QCOLL_ENOTSUP;
+  }
+}
+
+}  // namespace qcoll

@@ -1,0 +1,88 @@
+// Internal plan object and the launchers behind the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "qcoll.h"
+
+namespace qcoll {
+
+void set_error(const std::string &msg);
+
+struct Plan {
+  int device = 0;
+  int N = 0, N_rho = 0, M = 0, rank = 0, precision = 0;
+  double L = 0, R = 0, omega = 0, b = 0;
+  bool b_follows_omega = true;
+  bool truncated = false;        // SVD truncation requested (any svd_rank >= 0)
+  bool mix_identity = true;      // B_s = A_s (no SVD rotation)
+  int schedule = 0;              // hot-loop schedule: 0 auto, 1 two-pass, 2 fused
+  double sigma_max = 0, sigma_min_kept = 0;
+
+  std::vector<double> rho, w_rho;          // radial rule
+  std::vector<double> sphere;              // [M][4]
+  std::vector<double> umix;                // [rank][N_rho] (rotation rows kept)
+
+  // device tables, element type = working precision T (float or double)
+  void *phase = nullptr;   // [N_rho*M][3][N] complex: per-axis shift factors b_d(n)
+  void *wq = nullptr;      // [M] half-sphere weights
+  void *V = nullptr;       // [2*npair][N^3] real: spectral factors of the gain / N^3 (zero-padded row)
+  void *lam = nullptr;     // [N^3] loss weights / N^3, always FP64
+  void *umix_d = nullptr;  // [rank][N_rho]
+  // FP64 device tables
+  double *ginv = nullptr;  // [25] (C C^T)^{-1} of the collision invariants on the grid
+  double *lam_p = nullptr; // [N_rho][N^3] per-node loss weights (untruncated plans; omega gradient)
+  double *dlog = nullptr;  // [N_rho] d ln(b rho_p^{4-2 omega}) / d omega
+  int *flag = nullptr;     // non-finite flag
+
+  int npair() const { return (rank + 1) / 2; }
+  long n3() const { return long(N) * N * N; }
+};
+
+// workspace layout for one call; sizes in bytes, offsets 256-aligned
+struct Layout {
+  long bc = 0;          // items per chunk
+  long pc = 0;          // (item, radial node) pairs per hot-loop launch
+  size_t off_h = 0, off_h64 = 0, off_a = 0, off_b = 0, off_w = 0, off_t = 0, off_l = 0, off_y = 0;
+  size_t off_g = 0, off_z = 0, off_hp = 0, off_d = 0;  // vjp extras
+  size_t total = 0;
+};
+
+Layout make_layout(const Plan &p, int64_t batch, int op);
+
+qcoll_status launch_eval(const Plan &p, int64_t batch, const double *f, double *Q, void *ws,
+                         const Layout &lay, hipStream_t st);
+qcoll_status launch_conserve(const Plan &p, int64_t batch, double *Q, double *mom, hipStream_t st);
+qcoll_status launch_project(const Plan &p, int64_t batch, const double *in, double *out,
+                            hipStream_t st);
+qcoll_status launch_moments(const Plan &p, int64_t batch, const double *f, double *out,
+                            hipStream_t st);
+qcoll_status launch_vjp(const Plan &p, int64_t batch, const double *f, const double *g,
+                        double *df, double *domega, void *ws, const Layout &lay, hipStream_t st);
+
+bool supported_N(int N);
+bool fused_gain_supported(int N, int precision);
+bool use_fused_gain(const Plan &p);
+qcoll_status launch_gain_fused(const Plan &p, const void *H, void *A, long nbp, hipStream_t st);
+
+// kernel timing (hipEvents on the launch stream) for roofline accounting
+bool timing_on();
+void timing_begin(const char *name, hipStream_t st);
+void timing_end(const char *name, hipStream_t st);
+
+struct TimedLaunch {
+  const char *name;
+  hipStream_t st;
+  bool on;
+  TimedLaunch(const char *n, hipStream_t s) : name(n), st(s), on(timing_on()) {
+    if (on) timing_begin(name, st);
+  }
+  ~TimedLaunch() {
+    if (on) timing_end(name, st);
+  }
+};
+
+}  // namespace qcoll

@@ -1,0 +1,619 @@
+// Batched kernels of the fast spectral collision operator (gfx950).
+//
+// Every 3-D transform is split in two passes over HBM:
+//   slab pass   : one workgroup holds SPB slabs (fixed first index) in LDS and
+//                 transforms the two inner axes (rows in registers, then
+//                 columns), with coalesced loads/stores of whole slabs;
+//   pencil pass : one lane holds one pencil along the outer axis (stride N^2,
+//                 coalesced across lanes) and transforms it in registers.
+// The pointwise work of the method is fused into these passes:
+//   - the shift multiplier of each (rho_p, sigma_q) term into the slab load,
+//   - the product t1 t2 and the sphere sum into the pencil pass,
+//   - the low-rank weights, the loss multiplier and the final assembly into
+//     the last passes.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <type_traits>
+
+#include "qcoll_fft.hpp"
+#include "qcoll_internal.h"
+
+namespace qcoll {
+
+template <typename T>
+using C = cplx<T>;
+
+// slabs per workgroup: keep the LDS tile (re + im, padded rows) within 64 KiB
+template <typename T, int N>
+constexpr int spb() {
+  constexpr int by_lds = 65536 / (2 * N * (N + 1) * int(sizeof(T)));
+  constexpr int by_threads = 256 / N;
+  constexpr int s = by_lds < by_threads ? by_lds : by_threads;
+  return s < 1 ? 1 : s;
+}
+
+// 2-D transform of the SPB slabs held in LDS: rows (last axis), then columns.
+template <typename T, int N, int SPB, int SIGN>
+__device__ __forceinline__ void lds_slab_fft(T (*sre)[N][N + 1], T (*sim)[N][N + 1]) {
+  const int tid = threadIdx.x;
+  const int s = tid / N, r = tid % N;
+  T xr[N], xi[N];
+  static_for<0, N>([&](auto c) {
+    xr[decltype(c)::value] = sre[s][r][decltype(c)::value];
+    xi[decltype(c)::value] = sim[s][r][decltype(c)::value];
+  });
+  fft_reg<N, SIGN, T>(xr, xi);
+  static_for<0, N>([&](auto c) {
+    sre[s][r][decltype(c)::value] = xr[decltype(c)::value];
+    sim[s][r][decltype(c)::value] = xi[decltype(c)::value];
+  });
+  __syncthreads();
+  static_for<0, N>([&](auto rr) {
+    xr[decltype(rr)::value] = sre[s][decltype(rr)::value][r];
+    xi[decltype(rr)::value] = sim[s][decltype(rr)::value][r];
+  });
+  fft_reg<N, SIGN, T>(xr, xi);
+  static_for<0, N>([&](auto rr) {
+    sre[s][decltype(rr)::value][r] = xr[decltype(rr)::value];
+    sim[s][decltype(rr)::value][r] = xi[decltype(rr)::value];
+  });
+  __syncthreads();
+}
+
+// ----------------------------------------------------------------------------
+// Generic slab kernel: Src(g, r, c) -> C<T> loads element (r, c) of slab g with
+// any prologue; Dst(g, r, c, v) stores.  Slabs g >= nslab are skipped.
+template <typename T, int N, int SIGN, class Src, class Dst>
+__global__ __launch_bounds__(256) void k_slab(Src src, Dst dst, long nslab) {
+  constexpr int SPB = spb<T, N>();
+  __shared__ T sre[SPB][N][N + 1];
+  __shared__ T sim[SPB][N][N + 1];
+  const long g0 = long(blockIdx.x) * SPB;
+  for (int e = threadIdx.x; e < SPB * N * N; e += SPB * N) {
+    const int s = e / (N * N), rc = e % (N * N), r = rc / N, c = rc % N;
+    const long g = g0 + s;
+    C<T> v{T(0), T(0)};
+    if (g < nslab) v = src(g, r, c);
+    sre[s][r][c] = v.re;
+    sim[s][r][c] = v.im;
+  }
+  __syncthreads();
+  lds_slab_fft<T, N, SPB, SIGN>(sre, sim);
+  for (int e = threadIdx.x; e < SPB * N * N; e += SPB * N) {
+    const int s = e / (N * N), rc = e % (N * N), r = rc / N, c = rc % N;
+    const long g = g0 + s;
+    if (g < nslab) dst(g, r, c, C<T>{sre[s][r][c], sim[s][r][c]});
+  }
+}
+
+// generic pencil kernel: Op(pencil_group, r) with r = j2*N + j3
+template <int N, class Op>
+__global__ __launch_bounds__(256) void k_pencil(Op op, long npencil) {
+  const long pid = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (pid >= npencil) return;
+  op(pid / (N * N), int(pid % (N * N)));
+}
+
+// ----------------------------------------------------------------------------
+// functors
+
+// real FP64 input -> complex T, slab g = item*N + j1
+template <typename T, int N>
+struct SrcReal {
+  const double *f;
+  __device__ C<T> operator()(long g, int r, int c) const {
+    return C<T>{T(f[(g * N + r) * N + c]), T(0)};
+  }
+};
+
+template <typename T, int N>
+struct DstCplx {
+  C<T> *out;
+  __device__ void operator()(long g, int r, int c, C<T> v) const { out[(g * N + r) * N + c] = v; }
+};
+
+template <typename T, int N>
+struct SrcCplx {
+  const C<T> *in;
+  __device__ C<T> operator()(long g, int r, int c) const { return in[(g * N + r) * N + c]; }
+};
+
+// hot loop, slab pass: task t = (bp_local, q) with bp = bp0 + bp_local,
+// b = bp / N_rho, p = bp % N_rho; slab g = t*N + k1.  Loads H[b] times the
+// real multiplier c_s = Re beta_s + Im beta_s, beta_s = b1(k1) b2(k2) b3(k3),
+// scaled by 1/N^3 (normalised inverse).
+template <typename T, int N>
+struct SrcShift {
+  const C<T> *H;
+  const C<T> *phase;
+  long bp0;
+  int M, Nr;
+  T scale;
+  __device__ C<T> operator()(long g, int r, int c) const {
+    const long t = g / N;
+    const int k1 = int(g % N);
+    const long bp = bp0 + t / M;
+    const int q = int(t % M);
+    const long b = bp / Nr;
+    const int p = int(bp % Nr);
+    const C<T> *ph = phase + size_t(p * M + q) * 3 * N;
+    const C<T> b1 = ph[k1], b2 = ph[N + r], b3 = ph[2 * N + c];
+    const T x12 = b1.re * b2.re - b1.im * b2.im, y12 = b1.re * b2.im + b1.im * b2.re;
+    const T x = x12 * b3.re - y12 * b3.im, y = x12 * b3.im + y12 * b3.re;
+    const T m = (x + y) * scale;
+    const C<T> h = H[((b * N + k1) * N + r) * N + c];
+    return C<T>{h.re * m, h.im * m};
+  }
+};
+
+// hot loop, pencil pass: for each (b, p) and pencil (j2, j3), inverse
+// transform along the first axis for every q and accumulate
+// A_p += w_q (u_re^2 - u_im^2)  (= w_q t1 t2 with t1 = re - im, t2 = re + im).
+template <typename T, int N>
+struct OpGainAcc {
+  const C<T> *Y;
+  const T *wq;
+  T *A;
+  long bp0;
+  int M;
+  __device__ void operator()(long bpl, int r) const {
+    constexpr long n2 = long(N) * N, n3 = n2 * N;
+    T acc[N];
+    static_for<0, N>([&](auto j) { acc[decltype(j)::value] = T(0); });
+    for (int q = 0; q < M; ++q) {
+      const C<T> *y = Y + (bpl * M + q) * n3 + r;
+      T xr[N], xi[N];
+      static_for<0, N>([&](auto k) {
+        const C<T> v = y[decltype(k)::value * n2];
+        xr[decltype(k)::value] = v.re;
+        xi[decltype(k)::value] = v.im;
+      });
+      fft_reg<N, +1, T>(xr, xi);
+      const T w = wq[q];
+      static_for<0, N>([&](auto j) {
+        constexpr int jj = decltype(j)::value;
+        acc[jj] += w * (xr[jj] * xr[jj] - xi[jj] * xi[jj]);
+      });
+    }
+    T *a = A + (bp0 + bpl) * n3 + r;
+    static_for<0, N>([&](auto j) { a[decltype(j)::value * n2] = acc[decltype(j)::value]; });
+  }
+};
+
+// forward pencil pass in place (first axis)
+template <typename T, int N, int SIGN>
+struct OpPencilInPlace {
+  C<T> *X;
+  __device__ void operator()(long v, int r) const {
+    constexpr long n2 = long(N) * N, n3 = n2 * N;
+    C<T> *x = X + v * n3 + r;
+    T xr[N], xi[N];
+    static_for<0, N>([&](auto k) {
+      const C<T> e = x[decltype(k)::value * n2];
+      xr[decltype(k)::value] = e.re;
+      xi[decltype(k)::value] = e.im;
+    });
+    fft_reg<N, SIGN, T>(xr, xi);
+    static_for<0, N>([&](auto k) { x[decltype(k)::value * n2] = C<T>{xr[decltype(k)::value], xi[decltype(k)::value]}; });
+  }
+};
+
+// low-rank mixing: B[b][s] = sum_p U[s][p] A[b][p]
+template <typename T>
+__global__ void k_mix(const T *A, const T *U, T *B, long nitems, int S, int Nr, long n3) {
+  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nitems * n3) return;
+  const long b = i / n3, j = i % n3;
+  for (int s = 0; s < S; ++s) {
+    T acc = T(0);
+    for (int p = 0; p < Nr; ++p) acc += U[s * Nr + p] * A[(b * Nr + p) * n3 + j];
+    B[(b * S + s) * n3 + j] = acc;
+  }
+}
+
+// low-rank stage, slab pass: slab g = (b*npair + s)*N + j1, Z = B[2s] + i B[2s+1]
+template <typename T, int N>
+struct SrcPair {
+  const T *B;
+  int S, npair;
+  __device__ C<T> operator()(long g, int r, int c) const {
+    constexpr long n3 = long(N) * N * N;
+    const long t = g / N;
+    const int j1 = int(g % N);
+    const long b = t / npair;
+    const int s = int(t % npair);
+    const long o = (long(j1) * N + r) * N + c;
+    const T re = B[(b * S + 2 * s) * n3 + o];
+    const T im = (2 * s + 1 < S) ? B[(b * S + 2 * s + 1) * n3 + o] : T(0);
+    return C<T>{re, im};
+  }
+};
+
+// low-rank stage, pencil pass: forward along the first axis for each pair s,
+// accumulating T += (V_2s - i V_2s+1) Z^_s (V already carries 1/N^3).
+// With Z = B_2s + i B_2s+1 and V real and even, Re ifft(T) = sum_s C_s B_s.
+template <typename T, int N>
+struct OpLowRank {
+  const C<T> *W;
+  const T *V;
+  C<T> *TA;
+  int npair;
+  __device__ void operator()(long b, int r) const {
+    constexpr long n2 = long(N) * N, n3 = n2 * N;
+    T tr[N], ti[N];
+    static_for<0, N>([&](auto k) { tr[decltype(k)::value] = T(0); ti[decltype(k)::value] = T(0); });
+    for (int s = 0; s < npair; ++s) {
+      const C<T> *w = W + (b * npair + s) * n3 + r;
+      T xr[N], xi[N];
+      static_for<0, N>([&](auto k) {
+        const C<T> e = w[decltype(k)::value * n2];
+        xr[decltype(k)::value] = e.re;
+        xi[decltype(k)::value] = e.im;
+      });
+      fft_reg<N, -1, T>(xr, xi);
+      const T *v0 = V + (2 * s) * n3 + r;
+      const T *v1 = V + (2 * s + 1) * n3 + r;
+      static_for<0, N>([&](auto k) {
+        constexpr int kk = decltype(k)::value;
+        const T a = v0[kk * n2], c = v1[kk * n2];
+        // (a - i c)(xr + i xi) = (a xr + c xi) + i (a xi - c xr)
+        tr[kk] += a * xr[kk] + c * xi[kk];
+        ti[kk] += a * xi[kk] - c * xr[kk];
+      });
+    }
+    C<T> *o = TA + b * n3 + r;
+    static_for<0, N>([&](auto k) { o[decltype(k)::value * n2] = C<T>{tr[decltype(k)::value], ti[decltype(k)::value]}; });
+  }
+};
+
+// loss, slab pass (FP64): Lambda * H64, slab g = item*N + k1
+template <int N>
+struct SrcLoss {
+  const C<double> *H;
+  const double *lam;
+  __device__ C<double> operator()(long g, int r, int c) const {
+    const long o = (g * N + r) * N + c;
+    const double l = lam[((g % N) * N + r) * N + c];
+    const C<double> h = H[o];
+    return C<double>{h.re * l, h.im * l};
+  }
+};
+
+// final pencil pass: inverse along the first axis of the gain accumulator (T)
+// and of the loss spectrum (FP64), then Q = Re(gain) - f * Re(loss) in FP64.
+template <typename T, int N>
+struct OpAssemble {
+  const C<T> *TA;
+  const C<double> *LH;
+  const double *f;
+  double *Q;
+  __device__ void operator()(long b, int r) const {
+    constexpr long n2 = long(N) * N, n3 = n2 * N;
+    double out[N];
+    {
+      T ar[N], ai[N];
+      const C<T> *x0 = TA + b * n3 + r;
+      static_for<0, N>([&](auto k) {
+        const C<T> a = x0[decltype(k)::value * n2];
+        ar[decltype(k)::value] = a.re;
+        ai[decltype(k)::value] = a.im;
+      });
+      fft_reg<N, +1, T>(ar, ai);
+      static_for<0, N>([&](auto j) { out[decltype(j)::value] = double(ar[decltype(j)::value]); });
+    }
+    {
+      double lr[N], li[N];
+      const C<double> *x1 = LH + b * n3 + r;
+      static_for<0, N>([&](auto k) {
+        const C<double> l = x1[decltype(k)::value * n2];
+        lr[decltype(k)::value] = l.re;
+        li[decltype(k)::value] = l.im;
+      });
+      fft_reg<N, +1, double>(lr, li);
+      const double *fb = f + b * n3 + r;
+      static_for<0, N>([&](auto j) {
+        constexpr int jj = decltype(j)::value;
+        out[jj] -= fb[jj * n2] * lr[jj];
+      });
+    }
+    double *qb = Q + b * n3 + r;
+    static_for<0, N>([&](auto j) { qb[decltype(j)::value * n2] = out[decltype(j)::value]; });
+  }
+};
+
+// FP64 spectrum -> working precision
+template <typename T>
+__global__ void k_cast(const C<double> *in, C<T> *out, long n) {
+  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = C<T>{T(in[i].re), T(in[i].im)};
+}
+
+// ----------------------------------------------------------------------------
+inline unsigned nblk(long n, int b) { return unsigned((n + b - 1) / b); }
+
+#define QC_LAUNCH_CHECK(what)                                           \
+  do {                                                                  \
+    hipError_t e_ = hipGetLastError();                                  \
+    if (e_ != hipSuccess) {                                             \
+      set_error(std::string(what) + ": " + hipGetErrorString(e_));      \
+      return QCOLL_EDEVICE;                                             \
+    }                                                                   \
+  } while (0)
+
+template <typename T, int N>
+struct Engine {
+  static constexpr int SPB = spb<T, N>();
+  static constexpr long n3 = long(N) * N * N;
+
+  template <class Src, class Dst, int SIGN>
+  static qcoll_status slab(Src s, Dst d, long nslab, hipStream_t st, const char *what) {
+    if (nslab <= 0) return QCOLL_OK;
+    TimedLaunch tl(what, st);
+    hipLaunchKernelGGL((k_slab<T, N, SIGN, Src, Dst>), dim3(nblk(nslab, SPB)), dim3(SPB * N), 0, st, s, d, nslab);
+    QC_LAUNCH_CHECK(what);
+    return QCOLL_OK;
+  }
+  template <class Op>
+  static qcoll_status pencil(Op op, long npencil, hipStream_t st, const char *what) {
+    if (npencil <= 0) return QCOLL_OK;
+    TimedLaunch tl(what, st);
+    hipLaunchKernelGGL((k_pencil<N, Op>), dim3(nblk(npencil, 256)), dim3(256), 0, st, op, npencil);
+    QC_LAUNCH_CHECK(what);
+    return QCOLL_OK;
+  }
+
+  // forward transform of nb real items into H (complex)
+  static qcoll_status forward(const double *f, C<T> *H, long nb, hipStream_t st) {
+    qcoll_status s;
+    if ((s = slab<SrcReal<T, N>, DstCplx<T, N>, -1>(SrcReal<T, N>{f}, DstCplx<T, N>{H}, nb * N, st, "forward slab")))
+      return s;
+    return pencil(OpPencilInPlace<T, N, -1>{H}, nb * N * N, st, "forward pencil");
+  }
+
+  // A[b][p] for items of this chunk: (b, p) pairs bp in [0, nb*Nr)
+  static qcoll_status gain_terms(const Plan &p, const C<T> *H, T *A, C<T> *Y, long nb, long pc,
+                                 hipStream_t st) {
+    const long nbp = nb * p.N_rho;
+    if constexpr (std::is_same<T, float>::value) {
+      if (use_fused_gain(p)) return launch_gain_fused(p, H, A, nbp, st);
+    }
+    const T scale = T(1.0 / double(n3));
+    for (long bp0 = 0; bp0 < nbp; bp0 += pc) {
+      const long cnt = (nbp - bp0 < pc) ? (nbp - bp0) : pc;
+      SrcShift<T, N> src{H, reinterpret_cast<const C<T> *>(p.phase), bp0, p.M, p.N_rho, scale};
+      qcoll_status s;
+      if ((s = slab<SrcShift<T, N>, DstCplx<T, N>, +1>(src, DstCplx<T, N>{Y}, cnt * p.M * N, st, "gain slab")))
+        return s;
+      OpGainAcc<T, N> op{Y, reinterpret_cast<const T *>(p.wq), A, bp0, p.M};
+      if ((s = pencil(op, cnt * N * N, st, "gain pencil"))) return s;
+    }
+    return QCOLL_OK;
+  }
+
+  static qcoll_status eval(const Plan &p, int64_t batch, const double *f, double *Q, void *ws,
+                           const Layout &lay, hipStream_t st) {
+    char *w = static_cast<char *>(ws);
+    C<T> *H = reinterpret_cast<C<T> *>(w + lay.off_h);
+    C<double> *H64 = reinterpret_cast<C<double> *>(w + lay.off_h64);
+    T *A = reinterpret_cast<T *>(w + lay.off_a);
+    T *B = reinterpret_cast<T *>(w + lay.off_b);
+    C<T> *W = reinterpret_cast<C<T> *>(w + lay.off_w);
+    C<T> *TA = reinterpret_cast<C<T> *>(w + lay.off_t);
+    C<double> *LH = reinterpret_cast<C<double> *>(w + lay.off_l);
+    C<T> *Y = reinterpret_cast<C<T> *>(w + lay.off_y);
+    const int S = p.rank, np = p.npair();
+    for (long b0 = 0; b0 < batch; b0 += lay.bc) {
+      const long nb = (batch - b0 < lay.bc) ? (batch - b0) : lay.bc;
+      const double *fb = f + b0 * n3;
+      qcoll_status s;
+      // spectrum of f in FP64 (shared by the gain and the loss)
+      if ((s = Engine<double, N>::forward(fb, H64, nb, st))) return s;
+      if constexpr (!std::is_same<T, double>::value) {
+        TimedLaunch tl("cast", st);
+        hipLaunchKernelGGL(k_cast<T>, dim3(nblk(nb * n3, 256)), dim3(256), 0, st, H64, H, nb * n3);
+        QC_LAUNCH_CHECK("cast");
+      }
+      if ((s = gain_terms(p, H, A, Y, nb, lay.pc, st))) return s;
+      const T *Bsrc = A;
+      if (!p.mix_identity) {
+        TimedLaunch tl("mix", st);
+        hipLaunchKernelGGL(k_mix<T>, dim3(nblk(nb * n3, 256)), dim3(256), 0, st, A,
+                           reinterpret_cast<const T *>(p.umix_d), B, nb, S, p.N_rho, n3);
+        QC_LAUNCH_CHECK("mix");
+        Bsrc = B;
+      }
+      if ((s = slab<SrcPair<T, N>, DstCplx<T, N>, -1>(SrcPair<T, N>{Bsrc, S, np}, DstCplx<T, N>{W}, nb * np * N, st,
+                                                        "low-rank slab")))
+        return s;
+      OpLowRank<T, N> lr{W, reinterpret_cast<const T *>(p.V), TA, np};
+      if ((s = pencil(lr, nb * N * N, st, "low-rank pencil"))) return s;
+      if ((s = slab<SrcCplx<T, N>, DstCplx<T, N>, +1>(SrcCplx<T, N>{TA}, DstCplx<T, N>{TA}, nb * N, st,
+                                                        "gain inverse slab")))
+        return s;
+      if ((s = Engine<double, N>::template slab<SrcLoss<N>, DstCplx<double, N>, +1>(
+               SrcLoss<N>{H64, reinterpret_cast<const double *>(p.lam)}, DstCplx<double, N>{LH}, nb * N, st,
+               "loss slab")))
+        return s;
+      if ((s = pencil(OpAssemble<T, N>{TA, LH, fb, Q + b0 * n3}, nb * N * N, st, "assemble"))) return s;
+    }
+    return QCOLL_OK;
+  }
+};
+
+// ----------------------------------------------------------------------------
+// FP64 conservation projection: one workgroup per item.
+__global__ __launch_bounds__(256) void k_conserve(double *Q, double *mom, const double *ginv, int N, double L,
+                                                  int *flag, double dc3) {
+  const long n3 = long(N) * N * N;
+  const long b = blockIdx.x;
+  double *q = Q + b * n3;
+  const double dc = 2.0 * L / N;
+  double s[5] = {0, 0, 0, 0, 0};
+  for (long j = threadIdx.x; j < n3; j += blockDim.x) {
+    const int i1 = int(j / (N * N)), i2 = int((j / N) % N), i3 = int(j % N);
+    const double c1 = -L + (i1 + 0.5) * dc, c2 = -L + (i2 + 0.5) * dc, c3 = -L + (i3 + 0.5) * dc;
+    const double v = q[j];
+    s[0] += v;
+    s[1] += v * c1;
+    s[2] += v * c2;
+    s[3] += v * c3;
+    s[4] += v * (c1 * c1 + c2 * c2 + c3 * c3);
+  }
+  __shared__ double red[5][256];
+  for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = s[k];
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w)
+      for (int k = 0; k < 5; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  double m[5], lam[5];
+  for (int k = 0; k < 5; ++k) m[k] = red[k][0];
+  for (int a = 0; a < 5; ++a) {
+    double acc = 0;
+    for (int c = 0; c < 5; ++c) acc += ginv[a * 5 + c] * m[c];
+    lam[a] = acc;
+  }
+  bool finite = true;
+  for (int k = 0; k < 5; ++k) finite = finite && isfinite(m[k]);
+  if (threadIdx.x == 0) {
+    if (mom)
+      for (int k = 0; k < 5; ++k) mom[b * 5 + k] = m[k] * dc3;
+    if (!finite) atomicOr(flag, 1);
+  }
+  for (long j = threadIdx.x; j < n3; j += blockDim.x) {
+    const int i1 = int(j / (N * N)), i2 = int((j / N) % N), i3 = int(j % N);
+    const double c1 = -L + (i1 + 0.5) * dc, c2 = -L + (i2 + 0.5) * dc, c3 = -L + (i3 + 0.5) * dc;
+    q[j] -= lam[0] + lam[1] * c1 + lam[2] * c2 + lam[3] * c3 + lam[4] * (c1 * c1 + c2 * c2 + c3 * c3);
+  }
+}
+
+// Midpoint-rule moments, FP64, one workgroup per item, two passes.
+__global__ __launch_bounds__(256) void k_moments(const double *F, double *out, int N, double L) {
+  const long n3 = long(N) * N * N;
+  const long b = blockIdx.x;
+  const double *f = F + b * n3;
+  const double dc = 2.0 * L / N, dc3 = dc * dc * dc;
+  __shared__ double red[10][256];
+  double s[10];
+  for (int k = 0; k < 4; ++k) s[k] = 0;
+  for (long j = threadIdx.x; j < n3; j += blockDim.x) {
+    const int i1 = int(j / (N * N)), i2 = int((j / N) % N), i3 = int(j % N);
+    const double v = f[j];
+    s[0] += v;
+    s[1] += v * (-L + (i1 + 0.5) * dc);
+    s[2] += v * (-L + (i2 + 0.5) * dc);
+    s[3] += v * (-L + (i3 + 0.5) * dc);
+  }
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = s[k];
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w)
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  const double n = red[0][0] * dc3;
+  const double u1 = red[1][0] * dc3 / n, u2 = red[2][0] * dc3 / n, u3 = red[3][0] * dc3 / n;
+  __syncthreads();
+  for (int k = 0; k < 10; ++k) s[k] = 0;
+  for (long j = threadIdx.x; j < n3; j += blockDim.x) {
+    const int i1 = int(j / (N * N)), i2 = int((j / N) % N), i3 = int(j % N);
+    const double v = f[j];
+    const double d1 = -L + (i1 + 0.5) * dc - u1, d2 = -L + (i2 + 0.5) * dc - u2, d3 = -L + (i3 + 0.5) * dc - u3;
+    const double d2s = d1 * d1 + d2 * d2 + d3 * d3;
+    s[0] += v * d2s;
+    s[1] += v * d1 * d1;
+    s[2] += v * d1 * d2;
+    s[3] += v * d1 * d3;
+    s[4] += v * d2 * d2;
+    s[5] += v * d2 * d3;
+    s[6] += v * d3 * d3;
+    s[7] += v * d1 * d2s;
+    s[8] += v * d2 * d2s;
+    s[9] += v * d3 * d2s;
+  }
+  for (int k = 0; k < 10; ++k) red[k][threadIdx.x] = s[k];
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w)
+      for (int k = 0; k < 10; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double *o = out + b * 14;
+    o[0] = n;
+    o[1] = u1;
+    o[2] = u2;
+    o[3] = u3;
+    o[4] = 2.0 / (3.0 * n) * red[0][0] * dc3;
+    for (int k = 0; k < 6; ++k) o[5 + k] = 2.0 * red[1 + k][0] * dc3;
+    for (int k = 0; k < 3; ++k) o[11 + k] = red[7 + k][0] * dc3;
+  }
+}
+
+// ----------------------------------------------------------------------------
+bool use_fused_gain(const Plan &p) {
+  return p.schedule != 1 && fused_gain_supported(p.N, p.precision);
+}
+
+Layout make_layout(const Plan &p, int64_t batch, int op) {
+  Layout l;
+  const size_t es = (p.precision == QCOLL_FP32) ? sizeof(float) : sizeof(double);
+  const long n3 = p.n3();
+  l.bc = batch < 64 ? (batch > 0 ? batch : 1) : 64;
+  l.pc = 128;
+  if (l.pc > l.bc * p.N_rho) l.pc = l.bc * p.N_rho;
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  size_t o = 0;
+  l.off_h = o; o += al(size_t(l.bc) * n3 * 2 * es);
+  l.off_h64 = l.off_h;
+  if (p.precision == QCOLL_FP32) { l.off_h64 = o; o += al(size_t(l.bc) * n3 * 2 * sizeof(double)); }
+  l.off_a = o; o += al(size_t(l.bc) * p.N_rho * n3 * es);
+  l.off_b = o; o += p.mix_identity ? 0 : al(size_t(l.bc) * p.rank * n3 * es);
+  l.off_w = o; o += al(size_t(l.bc) * p.npair() * n3 * 2 * es);
+  l.off_t = o; o += al(size_t(l.bc) * n3 * 2 * es);
+  l.off_l = o; o += al(size_t(l.bc) * n3 * 2 * sizeof(double));
+  l.off_y = o; o += use_fused_gain(p) ? 0 : al(size_t(l.pc) * p.M * n3 * 2 * es);
+  (void)op;
+  l.total = o;
+  return l;
+}
+
+template <typename T>
+static qcoll_status eval_dispatch(const Plan &p, int64_t batch, const double *f, double *Q, void *ws,
+                                  const Layout &lay, hipStream_t st) {
+  switch (p.N) {
+    case 8: return Engine<T, 8>::eval(p, batch, f, Q, ws, lay, st);
+    case 12: return Engine<T, 12>::eval(p, batch, f, Q, ws, lay, st);
+    case 16: return Engine<T, 16>::eval(p, batch, f, Q, ws, lay, st);
+    case 24: return Engine<T, 24>::eval(p, batch, f, Q, ws, lay, st);
+    case 32: return Engine<T, 32>::eval(p, batch, f, Q, ws, lay, st);
+    case 48: return Engine<T, 48>::eval(p, batch, f, Q, ws, lay, st);
+    default: set_error("unsupported N"); return QCOLL_ENOTSUP;
+  }
+}
+
+qcoll_status launch_eval(const Plan &p, int64_t batch, const double *f, double *Q, void *ws,
+                         const Layout &lay, hipStream_t st) {
+  if (p.precision == QCOLL_FP32) return eval_dispatch<float>(p, batch, f, Q, ws, lay, st);
+  return eval_dispatch<double>(p, batch, f, Q, ws, lay, st);
+}
+
+qcoll_status launch_conserve(const Plan &p, int64_t batch, double *Q, double *mom, hipStream_t st) {
+  const double dc = 2.0 * p.L / p.N;
+  TimedLaunch tl("conserve", st);
+  hipLaunchKernelGGL(k_conserve, dim3(unsigned(batch)), dim3(256), 0, st, Q, mom, p.ginv, p.N, p.L, p.flag,
+                     dc * dc * dc);
+  QC_LAUNCH_CHECK("conserve");
+  return QCOLL_OK;
+}
+
+qcoll_status launch_moments(const Plan &p, int64_t batch, const double *f, double *out, hipStream_t st) {
+  TimedLaunch tl("moments", st);
+  hipLaunchKernelGGL(k_moments, dim3(unsigned(batch)), dim3(256), 0, st, f, out, p.N, p.L);
+  QC_LAUNCH_CHECK("moments");
+  return QCOLL_OK;
+}
+
+}  // namespace qcoll

@@ -1,0 +1,387 @@
+// Plan precompute on the host in FP64: quadratures, kernel-mode tables, shift
+// tables, optional SVD of the gain-weight table; then upload to the device.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "qcoll_internal.h"
+
+namespace qcoll {
+
+namespace {
+
+constexpr double kPiD = 3.141592653589793238462643383279502884;
+
+// Gauss-Legendre nodes/weights on [a, b] by Newton iteration on P_n.
+void gauss_legendre(int n, double a, double b, std::vector<double> &x, std::vector<double> &w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(kPiD * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      double pn = (n == 1) ? z : p1;
+      double pm = (n == 1) ? 1.0 : p0;
+      dp = n * (z * pn - pm) / (z * z - 1.0);
+      double dz = pn / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-17) break;
+    }
+    // recompute derivative at the converged node
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    double pn = (n == 1) ? z : p1, pm = (n == 1) ? 1.0 : p0;
+    dp = n * (z * pn - pm) / (z * z - 1.0);
+    // nodes ascending in [a, b]
+    x[n - 1 - i] = 0.5 * (b - a) * z + 0.5 * (b + a);
+    w[n - 1 - i] = (b - a) / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// built-in half-sphere rule: one vertex per antipodal pair of the icosahedron
+void icosahedral_half(std::vector<double> &s) {
+  const double ph = 0.5 * (1.0 + std::sqrt(5.0));
+  const double nrm = std::sqrt(1.0 + ph * ph);
+  const double a = 1.0 / nrm, c = ph / nrm;
+  const double pts[6][3] = {{0, a, c}, {0, -a, c}, {a, c, 0}, {-a, c, 0}, {c, 0, a}, {c, 0, -a}};
+  s.resize(24);
+  for (int i = 0; i < 6; ++i) {
+    s[4 * i + 0] = pts[i][0];
+    s[4 * i + 1] = pts[i][1];
+    s[4 * i + 2] = pts[i][2];
+    s[4 * i + 3] = 2.0 * kPiD / 6.0;
+  }
+}
+
+double sinc(double z) { return z == 0.0 ? 1.0 : std::sin(z) / z; }
+
+int kappa(int n, int N) { return n < N / 2 ? n : n - N; }
+
+// One-sided Jacobi: rotate the rows of A [m][n] until pairwise orthogonal.
+// On return A holds J A (orthogonal rows) and J [m][m] the accumulated rotation.
+void jacobi_rows(std::vector<double> &A, int m, long n, std::vector<double> &J) {
+  J.assign(size_t(m) * m, 0.0);
+  for (int i = 0; i < m; ++i) J[size_t(i) * m + i] = 1.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < m - 1; ++i) {
+      for (int j = i + 1; j < m; ++j) {
+        double *ri = &A[size_t(i) * n], *rj = &A[size_t(j) * n];
+        double a = 0, b = 0, c = 0;
+        for (long k = 0; k < n; ++k) {
+          a += ri[k] * ri[k];
+          b += rj[k] * rj[k];
+          c += ri[k] * rj[k];
+        }
+        if (a == 0.0 || b == 0.0) continue;
+        double rel = std::fabs(c) / std::sqrt(a * b);
+        off = std::max(off, rel);
+        if (rel < 1e-16) continue;
+        double zeta = (b - a) / (2.0 * c);
+        double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        double cs = 1.0 / std::sqrt(1.0 + t * t), sn = cs * t;
+        for (long k = 0; k < n; ++k) {
+          double x = ri[k], y = rj[k];
+          ri[k] = cs * x - sn * y;
+          rj[k] = sn * x + cs * y;
+        }
+        double *Ji = &J[size_t(i) * m], *Jj = &J[size_t(j) * m];
+        for (int k = 0; k < m; ++k) {
+          double x = Ji[k], y = Jj[k];
+          Ji[k] = cs * x - sn * y;
+          Jj[k] = sn * x + cs * y;
+        }
+      }
+    }
+    if (off < 1e-15) break;
+  }
+}
+
+template <typename T>
+qcoll_status upload(const std::vector<double> &h, void **dptr) {
+  std::vector<T> t(h.begin(), h.end());
+  if (hipMalloc(dptr, t.size() * sizeof(T)) != hipSuccess) {
+    *dptr = nullptr;
+    set_error("hipMalloc failed for a plan table");
+    return QCOLL_ENOMEM;
+  }
+  if (hipMemcpy(*dptr, t.data(), t.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+    set_error("hipMemcpy failed for a plan table");
+    return QCOLL_EDEVICE;
+  }
+  return QCOLL_OK;
+}
+
+}  // namespace
+
+bool supported_N(int N) {
+  return N == 8 || N == 12 || N == 16 || N == 24 || N == 32 || N == 48;
+}
+
+// Kernel tables for the current omega/prefactor (alpha_p rows, Lambda, Lambda_p).
+static void kernel_tables(const Plan &p, std::vector<double> &alpha, std::vector<double> &lam,
+                          std::vector<double> &lam_p) {
+  const int N = p.N;
+  const long n3 = p.n3();
+  double wsum = 0;
+  for (int q = 0; q < p.M; ++q) wsum += p.sphere[4 * q + 3];
+  alpha.assign(size_t(p.N_rho) * n3, 0.0);
+  lam.assign(n3, 0.0);
+  lam_p.assign(size_t(p.N_rho) * n3, 0.0);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j)
+      for (int k = 0; k < N; ++k) {
+        const double k1 = kappa(i, N), k2 = kappa(j, N), k3 = kappa(k, N);
+        const double ka = std::sqrt(k1 * k1 + k2 * k2 + k3 * k3);
+        const long idx = (long(i) * N + j) * N + k;
+        for (int r = 0; r < p.N_rho; ++r) {
+          const double rr = p.rho[r], wr = p.w_rho[r];
+          const double c = 4.0 * kPiD * p.b * std::pow(rr, 4.0 - 2.0 * p.omega);
+          // gain: 2 w_p F(k, rho_p); F = 4 pi b rho^{4-2w} sinc(pi rho |k| / (2L))
+          alpha[size_t(r) * n3 + idx] = 2.0 * wr * c * sinc(kPiD * rr * ka / (2.0 * p.L));
+          // loss: 2 (sum_q w_q) w_p F(2k, rho_p)
+          const double lp = 2.0 * wsum * wr * c * sinc(kPiD * rr * ka / p.L);
+          lam_p[size_t(r) * n3 + idx] = lp;
+          lam[idx] += lp;
+        }
+      }
+}
+
+static qcoll_status upload_kernel_tables(Plan &p) {
+  std::vector<double> alpha, lam, lam_p;
+  kernel_tables(p, alpha, lam, lam_p);
+  const int m = p.N_rho;
+  const long n3 = p.n3();
+  std::vector<double> V, U;
+  p.truncated = false;
+  p.mix_identity = true;
+  p.rank = m;
+  p.sigma_max = p.sigma_min_kept = 0.0;
+  V = alpha;
+  U.assign(size_t(m) * m, 0.0);
+  for (int i = 0; i < m; ++i) U[size_t(i) * m + i] = 1.0;
+  // V rows scaled by 1/N^3 (normalised inverse transform), padded to an even count
+  const double inv = 1.0 / double(n3);
+  const int rows = 2 * p.npair();
+  std::vector<double> Vs(size_t(rows) * n3, 0.0);
+  for (size_t i = 0; i < size_t(p.rank) * n3; ++i) Vs[i] = V[i] * inv;
+  std::vector<double> lams(lam);
+  for (auto &x : lams) x *= inv;
+  qcoll_status st;
+  auto up = [&](const std::vector<double> &h, void **d) {
+    return p.precision == QCOLL_FP32 ? upload<float>(h, d) : upload<double>(h, d);
+  };
+  if ((st = up(Vs, &p.V)) != QCOLL_OK) return st;
+  if ((st = upload<double>(lams, &p.lam)) != QCOLL_OK) return st;
+  if ((st = up(U, &p.umix_d)) != QCOLL_OK) return st;
+  p.umix = U;
+  if ((st = upload<double>(lam_p, reinterpret_cast<void **>(&p.lam_p))) != QCOLL_OK) return st;
+  std::vector<double> dl(m);
+  double dlb = 0.0;
+  if (p.b_follows_omega) {
+    // d ln b / d omega = ln 2 + psi(2.5 - omega); psi by recurrence + asymptotic series
+    double x = 2.5 - p.omega, acc = 0.0;
+    while (x < 8.0) { acc -= 1.0 / x; x += 1.0; }
+    const double x2 = 1.0 / (x * x);
+    const double psi = acc + std::log(x) - 0.5 / x -
+                       x2 * (1.0 / 12 - x2 * (1.0 / 120 - x2 * (1.0 / 252 - x2 * (1.0 / 240 - x2 / 132))));
+    dlb = std::log(2.0) + psi;
+  }
+  for (int r = 0; r < m; ++r) dl[r] = dlb - 2.0 * std::log(p.rho[r]);
+  return upload<double>(dl, reinterpret_cast<void **>(&p.dlog));
+}
+
+static qcoll_status upload_truncated(Plan &p, int svd_rank, double svd_tol) {
+  std::vector<double> alpha, lam, lam_p;
+  kernel_tables(p, alpha, lam, lam_p);
+  const int m = p.N_rho;
+  const long n3 = p.n3();
+  std::vector<double> J;
+  jacobi_rows(alpha, m, n3, J);
+  std::vector<double> nrm(m);
+  for (int i = 0; i < m; ++i) {
+    double s = 0;
+    for (long k = 0; k < n3; ++k) s += alpha[size_t(i) * n3 + k] * alpha[size_t(i) * n3 + k];
+    nrm[i] = std::sqrt(s);
+  }
+  std::vector<int> ord(m);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) { return nrm[a] > nrm[b]; });
+  int r = m;
+  if (svd_rank > 0) {
+    r = std::min(svd_rank, m);
+  } else {
+    r = 0;
+    for (int i = 0; i < m; ++i)
+      if (nrm[ord[i]] > svd_tol * nrm[ord[0]]) ++r;
+    r = std::max(r, 1);
+  }
+  p.truncated = true;
+  p.mix_identity = false;
+  p.rank = r;
+  p.sigma_max = nrm[ord[0]];
+  p.sigma_min_kept = nrm[ord[r - 1]];
+  const int rows = 2 * p.npair();
+  const double inv = 1.0 / double(n3);
+  std::vector<double> Vs(size_t(rows) * n3, 0.0), U(size_t(r) * m);
+  for (int s = 0; s < r; ++s) {
+    for (long k = 0; k < n3; ++k) Vs[size_t(s) * n3 + k] = alpha[size_t(ord[s]) * n3 + k] * inv;
+    for (int q = 0; q < m; ++q) U[size_t(s) * m + q] = J[size_t(ord[s]) * m + q];
+  }
+  std::vector<double> lams(lam);
+  for (auto &x : lams) x *= inv;
+  qcoll_status st;
+  auto up = [&](const std::vector<double> &h, void **d) {
+    return p.precision == QCOLL_FP32 ? upload<float>(h, d) : upload<double>(h, d);
+  };
+  if ((st = up(Vs, &p.V)) != QCOLL_OK) return st;
+  if ((st = upload<double>(lams, &p.lam)) != QCOLL_OK) return st;
+  if ((st = up(U, &p.umix_d)) != QCOLL_OK) return st;
+  p.umix = U;
+  return QCOLL_OK;
+}
+
+static void free_kernel_tables(Plan &p) {
+  hipFree(p.V);
+  hipFree(p.lam);
+  hipFree(p.umix_d);
+  hipFree(p.lam_p);
+  hipFree(p.dlog);
+  p.V = p.lam = p.umix_d = nullptr;
+  p.lam_p = p.dlog = nullptr;
+}
+
+qcoll_status plan_build(Plan &p, const qcoll_params &prm) {
+  p.N = prm.N;
+  p.L = prm.L;
+  p.N_rho = prm.N_rho;
+  p.omega = prm.omega;
+  p.precision = prm.precision;
+  p.b_follows_omega = !(prm.prefactor > 0.0);
+  p.b = p.b_follows_omega ? 1.0 / (std::pow(2.0, 3.0 - p.omega) * std::tgamma(2.5 - p.omega) * kPiD)
+                          : prm.prefactor;
+  p.R = 4.0 * p.L / (3.0 + std::sqrt(2.0));
+  gauss_legendre(p.N_rho, 0.0, p.R, p.rho, p.w_rho);
+  if (prm.sphere) {
+    p.M = prm.M;
+    p.sphere.assign(prm.sphere, prm.sphere + 4 * size_t(prm.M));
+  } else {
+    p.M = 6;
+    icosahedral_half(p.sphere);
+  }
+  if (hipGetDevice(&p.device) != hipSuccess) {
+    set_error("hipGetDevice failed");
+    return QCOLL_EDEVICE;
+  }
+  const int N = p.N;
+  // per-axis shift factors b_d(n) for s = rho_p sigma_q / 2
+  std::vector<double> ph(size_t(p.N_rho) * p.M * 3 * N * 2);
+  for (int r = 0; r < p.N_rho; ++r)
+    for (int q = 0; q < p.M; ++q)
+      for (int d = 0; d < 3; ++d) {
+        const double s = 0.5 * p.rho[r] * p.sphere[4 * q + d];
+        for (int n = 0; n < N; ++n) {
+          const double th = kPiD * kappa(n, N) * s / p.L;
+          double re = std::cos(th), im = std::sin(th);
+          if (n == N / 2) im = 0.0;  // cosine mode of the real interpolant
+          const size_t o = ((((size_t(r) * p.M + q) * 3 + d) * N) + n) * 2;
+          ph[o] = re;
+          ph[o + 1] = im;
+        }
+      }
+  std::vector<double> wq(p.M);
+  for (int q = 0; q < p.M; ++q) wq[q] = p.sphere[4 * q + 3];
+  qcoll_status st;
+  if (p.precision == QCOLL_FP32) {
+    if ((st = upload<float>(ph, &p.phase)) != QCOLL_OK) return st;
+    if ((st = upload<float>(wq, &p.wq)) != QCOLL_OK) return st;
+  } else {
+    if ((st = upload<double>(ph, &p.phase)) != QCOLL_OK) return st;
+    if ((st = upload<double>(wq, &p.wq)) != QCOLL_OK) return st;
+  }
+  // conservation: G = C C^T over the grid, inverted by Gauss-Jordan (5x5)
+  {
+    const double dc = 2.0 * p.L / N;
+    double G[5][5] = {};
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j)
+        for (int k = 0; k < N; ++k) {
+          const double c1 = -p.L + (i + 0.5) * dc, c2 = -p.L + (j + 0.5) * dc, c3 = -p.L + (k + 0.5) * dc;
+          const double v[5] = {1.0, c1, c2, c3, c1 * c1 + c2 * c2 + c3 * c3};
+          for (int a = 0; a < 5; ++a)
+            for (int b = 0; b < 5; ++b) G[a][b] += v[a] * v[b];
+        }
+    double A[5][10] = {};
+    for (int a = 0; a < 5; ++a) {
+      for (int b = 0; b < 5; ++b) A[a][b] = G[a][b];
+      A[a][5 + a] = 1.0;
+    }
+    for (int c = 0; c < 5; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < 5; ++r)
+        if (std::fabs(A[r][c]) > std::fabs(A[piv][c])) piv = r;
+      for (int k = 0; k < 10; ++k) std::swap(A[c][k], A[piv][k]);
+      const double d = A[c][c];
+      for (int k = 0; k < 10; ++k) A[c][k] /= d;
+      for (int r = 0; r < 5; ++r)
+        if (r != c) {
+          const double m = A[r][c];
+          for (int k = 0; k < 10; ++k) A[r][k] -= m * A[c][k];
+        }
+    }
+    std::vector<double> gi(25);
+    for (int a = 0; a < 5; ++a)
+      for (int b = 0; b < 5; ++b) gi[a * 5 + b] = A[a][5 + b];
+    if ((st = upload<double>(gi, reinterpret_cast<void **>(&p.ginv))) != QCOLL_OK) return st;
+  }
+  if (hipMalloc(&p.flag, sizeof(int)) != hipSuccess) {
+    set_error("hipMalloc failed for the status flag");
+    return QCOLL_ENOMEM;
+  }
+  if (hipMemset(p.flag, 0, sizeof(int)) != hipSuccess) {
+    set_error("hipMemset failed");
+    return QCOLL_EDEVICE;
+  }
+  if (prm.svd_rank < 0) return upload_kernel_tables(p);
+  return upload_truncated(p, prm.svd_rank, prm.svd_tol);
+}
+
+qcoll_status plan_set_omega(Plan &p, double omega) {
+  if (p.truncated) {
+    set_error("qcoll_plan_set_omega needs an untruncated plan");
+    return QCOLL_ENOTSUP;
+  }
+  if (hipDeviceSynchronize() != hipSuccess) {
+    set_error("hipDeviceSynchronize failed");
+    return QCOLL_EDEVICE;
+  }
+  free_kernel_tables(p);
+  p.omega = omega;
+  if (p.b_follows_omega)
+    p.b = 1.0 / (std::pow(2.0, 3.0 - p.omega) * std::tgamma(2.5 - p.omega) * kPiD);
+  return upload_kernel_tables(p);
+}
+
+void plan_free(Plan &p) {
+  free_kernel_tables(p);
+  hipFree(p.phase);
+  hipFree(p.wq);
+  hipFree(p.ginv);
+  hipFree(p.flag);
+  p.phase = p.wq = nullptr;
+  p.ginv = nullptr;
+  p.flag = nullptr;
+}
+
+}  // namespace qcoll

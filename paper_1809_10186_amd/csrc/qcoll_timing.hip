@@ -1,0 +1,111 @@
+// Process-wide kernel timer: hipEvent pairs on the launch stream, per role name.
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "qcoll_internal.h"
+
+namespace qcoll {
+namespace {
+
+struct Rec {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  size_t open = 0;  // index of the pair awaiting its stop event
+};
+
+bool g_on = false;
+std::map<std::string, Rec> g_recs;
+
+hipEvent_t make_event() {
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+}  // namespace
+
+bool timing_on() { return g_on; }
+
+void timing_begin(const char *name, hipStream_t st) {
+  Rec &r = g_recs[name];
+  hipEvent_t a = make_event(), b = make_event();
+  if (!a || !b) return;
+  hipEventRecord(a, st);
+  r.ev.emplace_back(a, b);
+  r.open = r.ev.size();
+}
+
+void timing_end(const char *name, hipStream_t st) {
+  auto it = g_recs.find(name);
+  if (it == g_recs.end() || it->second.open == 0) return;
+  hipEventRecord(it->second.ev[it->second.open - 1].second, st);
+  it->second.open = 0;
+}
+
+}  // namespace qcoll
+
+extern "C" {
+
+qcoll_status qcoll_timing_enable(int32_t on) {
+  qcoll::g_on = on != 0;
+  return QCOLL_OK;
+}
+
+qcoll_status qcoll_timing_reset(void) {
+  for (auto &kv : qcoll::g_recs)
+    for (auto &e : kv.second.ev) {
+      hipEventSynchronize(e.second);
+      hipEventDestroy(e.first);
+      hipEventDestroy(e.second);
+    }
+  qcoll::g_recs.clear();
+  return QCOLL_OK;
+}
+
+qcoll_status qcoll_timing_read(const char *name, double *ms, int64_t *count) {
+  if (!name || !ms || !count) {
+    qcoll::set_error("NULL argument");
+    return QCOLL_EINVAL;
+  }
+  *ms = 0.0;
+  *count = 0;
+  auto it = qcoll::g_recs.find(name);
+  if (it == qcoll::g_recs.end()) return QCOLL_OK;
+  double tot = 0.0;
+  int64_t n = 0;
+  for (auto &e : it->second.ev) {
+    if (hipEventSynchronize(e.second) != hipSuccess) {
+      qcoll::set_error("hipEventSynchronize failed");
+      return QCOLL_EDEVICE;
+    }
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, e.first, e.second) != hipSuccess) {
+      qcoll::set_error("hipEventElapsedTime failed");
+      return QCOLL_EDEVICE;
+    }
+    tot += t;
+    ++n;
+  }
+  *ms = tot;
+  *count = n;
+  return QCOLL_OK;
+}
+
+qcoll_status qcoll_timing_names(char *buf, size_t cap) {
+  if (!buf || cap == 0) {
+    qcoll::set_error("NULL argument");
+    return QCOLL_EINVAL;
+  }
+  std::string s;
+  for (auto &kv : qcoll::g_recs) {
+    if (!s.empty()) s += '\n';
+    s += kv.first;
+  }
+  size_t n = s.size() < cap - 1 ? s.size() : cap - 1;
+  s.copy(buf, n);
+  buf[n] = '\0';
+  return QCOLL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,160 @@
+"""GPU parity of qcoll_eval / qcoll_conserve / qcoll_moments against the FP64 oracle.
+
+Tolerances (rel L-inf per item, normwise, max over items):
+  FP64 path <= 1e-12, FP32 path <= 2e-5 (relative to ||Q_oracle||_inf).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import conserve as oc
+from oracle import spectral
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1809_10186_amd as qc  # noqa: E402
+
+TOL = {qc.QCOLL_FP64: 1e-12, qc.QCOLL_FP32: 2e-5}
+
+
+def rel_linf(a, b):
+    a = a.reshape(a.shape[0], -1)
+    b = b.reshape(b.shape[0], -1)
+    return float(np.max(np.abs(a - b).max(axis=1) / np.abs(b).max(axis=1)))
+
+
+def gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def run_case(N, L, N_rho, M, omega, batch, precision, seed, svd_tol=None, prefactor=None, noise=0.01):
+    sph = W.sphere_rule(M)
+    f = W.maxwellian_mixture(batch, N, L, seed, noise=noise)
+    P = spectral.Params(N, L, N_rho, sph[0], sph[1], omega, prefactor=prefactor, svd_tol=svd_tol)
+    plan = qc.Plan(N, L, N_rho, sphere=sph, omega=omega, prefactor=prefactor,
+                   svd_rank=0 if svd_tol else -1, svd_tol=svd_tol or 0.0, precision=precision)
+    assert plan.info()["rank"] == P.rank
+    Q = plan.eval(gpu(f)).cpu().numpy()
+    Qref = spectral.collide_batch(f, P)
+    return f, Q, Qref, plan, P
+
+
+@pytest.mark.parametrize("precision", [qc.QCOLL_FP64, qc.QCOLL_FP32])
+@pytest.mark.parametrize("N,L,N_rho,M,batch", [(8, 4.0, 4, 6, 70), (12, 5.0, 6, 12, 5),
+                                               (16, 6.0, 8, 12, 3), (24, 6.0, 12, 12, 2)])
+def test_eval_matches_oracle(N, L, N_rho, M, batch, precision):
+    print(f"case N={N} batch={batch} prec={precision}", flush=True)
+    f, Q, Qref, _, _ = run_case(N, L, N_rho, M, 0.81, batch, precision, seed=100 + N)
+    err = rel_linf(Q, Qref)
+    print(f"rel_linf={err:.3e}", flush=True)
+    assert err <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", [qc.QCOLL_FP64, qc.QCOLL_FP32])
+def test_eval_truncated_gain_table(precision):
+    f, Q, Qref, plan, P = run_case(16, 6.0, 10, 12, 0.81, 3, precision, seed=7, svd_tol=1e-6)
+    assert P.rank < 10
+    assert rel_linf(Q, Qref) <= TOL[precision]
+
+
+def test_eval_bkw_maxwell_molecules():
+    # BKW at t0 = 5.5 on [-8, 8]^3, M = 6 built-in rule, B = 1/(4 pi)
+    N, L = 16, 8.0
+    f = W.bkw(N, L, 5.5)[None]
+    plan = qc.Plan(N, L, 8, sphere=None, omega=1.0, prefactor=1.0 / (4 * np.pi), precision=qc.QCOLL_FP64)
+    Q = plan.eval(gpu(f)).cpu().numpy()
+    sph = W.sphere_rule(6)
+    P = spectral.Params(N, L, 8, sph[0], sph[1], 1.0, prefactor=1.0 / (4 * np.pi))
+    assert rel_linf(Q, spectral.collide_batch(f, P)) <= 1e-12
+
+
+@pytest.mark.parametrize("precision", [qc.QCOLL_FP64, qc.QCOLL_FP32])
+def test_constant_f_gives_zero(precision):
+    f = np.full((2, 12, 12, 12), 0.25)
+    plan = qc.Plan(12, 5.0, 6, sphere=W.sphere_rule(12), omega=0.81, precision=precision)
+    Q = plan.eval(gpu(f)).cpu().numpy()
+    sph = W.sphere_rule(12)
+    P = spectral.Params(12, 5.0, 6, sph[0], sph[1], 0.81)
+    _, gp, lp, _ = spectral.collide(f[0], P, return_parts=True)
+    scale = np.abs(lp).max()
+    assert np.abs(Q).max() <= (1e-13 if precision == qc.QCOLL_FP64 else 1e-6) * scale
+
+
+@pytest.mark.parametrize("precision", [qc.QCOLL_FP64, qc.QCOLL_FP32])
+def test_conserve_matches_oracle_projection(precision):
+    N, L = 12, 5.0
+    f, Q, Qref, plan, _ = run_case(N, L, 6, 12, 0.81, 4, precision, seed=21)
+    Qg = gpu(Q)
+    mom = torch.empty((4, 5), dtype=torch.float64, device="cuda")
+    plan.conserve(Qg, mom)
+    plan.poll()
+    Qc = Qg.cpu().numpy()
+    Qc_ref, m_ref = oc.project(Q, N, L)
+    assert rel_linf(Qc, Qc_ref) <= 1e-12
+    dc3 = (2 * L / N) ** 3
+    assert np.allclose(mom.cpu().numpy(), m_ref * dc3, rtol=1e-12, atol=1e-14 * np.abs(Q).sum() * dc3)
+    assert np.all(oc.conservation_residual(Qc, N, L) <= 1e-12)
+
+
+def test_moments_match_oracle():
+    N, L = 16, 6.0
+    f = W.maxwellian_mixture(3, N, L, 5)
+    plan = qc.Plan(N, L, 4, sphere=None, omega=0.81)
+    m = plan.moments(gpu(f)).cpu().numpy()
+    ref = oc.moments(f, N, L)
+    assert np.allclose(m, ref, rtol=1e-12, atol=1e-13)
+
+
+def test_nonfinite_input_is_flagged():
+    N, L = 8, 4.0
+    plan = qc.Plan(N, L, 4, sphere=None, omega=0.81)
+    Q = torch.zeros((1, N, N, N), dtype=torch.float64, device="cuda")
+    Q[0, 1, 2, 3] = float("nan")
+    plan.conserve(Q)
+    with pytest.raises(qc.QcollError) as e:
+        plan.poll()
+    assert e.value.code == 6
+    plan.poll()   # flag cleared
+
+
+def test_error_paths_on_device():
+    N = 8
+    plan = qc.Plan(N, 4.0, 4, sphere=None, omega=0.81)
+    f = torch.ones((2, N, N, N), dtype=torch.float64, device="cuda")
+    import ctypes
+    L = qc.lib()
+    out = torch.empty_like(f)
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    code = L.qcoll_eval(plan._h, 2, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                        ctypes.c_void_p(small.data_ptr()), 16, None)
+    assert code == 5
+    code = L.qcoll_eval(plan._h, 2, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(f.data_ptr()),
+                        ctypes.c_void_p(small.data_ptr()), 1 << 40, None)
+    assert code == 1
+    assert L.qcoll_eval(plan._h, 0, None, None, None, 0, None) == 0
+    assert L.qcoll_eval(plan._h, -1, None, None, None, 0, None) == 1
+
+
+def test_dg1d_full_size_sampled_items():
+    """The 1D DG batch at full size (192 items, 32^3, M=12, N_rho=16, omega 0.81,
+    SVD at 1e-8), in the bench's launch configuration; sampled items vs oracle."""
+    w = W.WORKLOADS["dg1d_32"]
+    N, L = w["N"], w["L"]
+    f = W.mixture_for("dg1d_32")
+    sph = W.sphere_rule(w["M"])
+    P = spectral.Params(N, L, w["N_rho"], sph[0], sph[1], w["omega"], svd_tol=w["svd_tol"])
+    fg = gpu(f)
+    idx = [0, 97, 191]
+    Qref = np.stack([spectral.collide(f[i], P) for i in idx])
+    for prec in (qc.QCOLL_FP64, qc.QCOLL_FP32):
+        plan = qc.Plan(N, L, w["N_rho"], sphere=sph, omega=w["omega"], svd_rank=0,
+                       svd_tol=w["svd_tol"], precision=prec)
+        assert plan.info()["rank"] == P.rank
+        Q = plan.eval(fg)
+        err = rel_linf(Q.cpu().numpy()[idx], Qref)
+        print(f"prec={prec} rel_linf={err:.3e}", flush=True)
+        assert err <= TOL[prec]
+        plan.conserve(Q)
+        Qc = Q.cpu().numpy()
+        assert np.all(oc.conservation_residual(Qc, N, L) <= 1e-12)
