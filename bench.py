@@ -64,6 +64,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-acc", action="store_true")
     ap.add_argument("--cpu-items", type=int, default=0)
+    ap.add_argument("--schedule", type=int, default=0, help="hot-loop schedule of the FP32 plan (0 auto)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: every item is independent and the box has one GPU; "
@@ -84,6 +85,8 @@ def main():
     for prec in (qc.QCOLL_FP32, qc.QCOLL_FP64):
         plans[prec] = qc.Plan(N, L, w["N_rho"], sphere=sph, omega=w["omega"], svd_rank=0,
                               svd_tol=w["svd_tol"], precision=prec)
+        if prec == qc.QCOLL_FP32 and a.schedule:
+            plans[prec].set_schedule(a.schedule)
         plans[prec].workspace(B, 0)
     stream = torch.cuda.current_stream()
 

@@ -25,11 +25,23 @@
 
 namespace qcoll {
 
+// Raw buffer descriptor over [base, base + bytes): loads through it take the
+// per-element stride as a scalar offset (no per-element address VGPRs) and
+// return 0 outside the range instead of faulting.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, int(bytes), 0x00020000);
+}
+
+__device__ __forceinline__ cplx<float> load_c32(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  const float2 v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  return cplx<float>{v.x, v.y};
+}
+
 template <int N>
 struct FusedGeom {
-  // pencils per lane: two at N = 32 so that the 2 x 32 complex values plus the
-  // 2 x 32 accumulators of a lane fit the 256-VGPR budget of 512-lane groups
-  static constexpr int PPL = (N == 32) ? 2 : 1;
+  // pencils per lane (1: N^2 lanes; the loops below also support 2, which
+  // halves the lane count at twice the registers per lane)
+  static constexpr int PPL = 1;
   static constexpr int NL = N * N / PPL;
   static constexpr int S1 = N * N + 32;
   static constexpr size_t lds_bytes = size_t(N) * S1 * sizeof(float);
@@ -88,7 +100,7 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<floa
     static_for<0, N>([&](auto j) { acc[decltype(u)::value][decltype(j)::value] = 0.f; });
   });
 
-  const cplx<float> *h = H + b * n3 + lane;
+  const __amdgpu_buffer_rsrc_t hr = make_rsrc(H + b * n3, unsigned(n3 * sizeof(cplx<float>)));
   for (int q = 0; q < M; ++q) {
     const cplx<float> *ph = phase + size_t(p * M + q) * 3 * N;
     float zr[PPL][N], zi[PPL][N];
@@ -101,7 +113,8 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<floa
       const float P = (xr + yi) * scale, Qm = (xr - yi) * scale;
       static_for<0, N>([&](auto k) {
         constexpr int kk = decltype(k)::value;
-        const cplx<float> v = h[kk * n2 + u * NL];
+        const cplx<float> v = load_c32(hr, int((lane + u * NL) * sizeof(cplx<float>)),
+                                       int(kk * n2 * sizeof(cplx<float>)));
         const cplx<float> b1 = ph[kk];
         const float c = b1.re * P + b1.im * Qm;
         zr[u][kk] = v.re * c;

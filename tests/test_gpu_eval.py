@@ -28,12 +28,15 @@ def gpu(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
 
 
-def run_case(N, L, N_rho, M, omega, batch, precision, seed, svd_tol=None, prefactor=None, noise=0.01):
+def run_case(N, L, N_rho, M, omega, batch, precision, seed, svd_tol=None, prefactor=None, noise=0.01,
+             schedule=0):
     sph = W.sphere_rule(M)
     f = W.maxwellian_mixture(batch, N, L, seed, noise=noise)
     P = spectral.Params(N, L, N_rho, sph[0], sph[1], omega, prefactor=prefactor, svd_tol=svd_tol)
     plan = qc.Plan(N, L, N_rho, sphere=sph, omega=omega, prefactor=prefactor,
                    svd_rank=0 if svd_tol else -1, svd_tol=svd_tol or 0.0, precision=precision)
+    if schedule:
+        plan.set_schedule(schedule)
     assert plan.info()["rank"] == P.rank
     Q = plan.eval(gpu(f)).cpu().numpy()
     Qref = spectral.collide_batch(f, P)
@@ -51,9 +54,10 @@ def test_eval_matches_oracle(N, L, N_rho, M, batch, precision):
     assert err <= TOL[precision]
 
 
-@pytest.mark.parametrize("precision", [qc.QCOLL_FP64, qc.QCOLL_FP32])
-def test_eval_truncated_gain_table(precision):
-    f, Q, Qref, plan, P = run_case(16, 6.0, 10, 12, 0.81, 3, precision, seed=7, svd_tol=1e-6)
+@pytest.mark.parametrize("precision,schedule", [(qc.QCOLL_FP64, 0), (qc.QCOLL_FP32, 0), (qc.QCOLL_FP32, 1)])
+def test_eval_truncated_gain_table(precision, schedule):
+    f, Q, Qref, plan, P = run_case(16, 6.0, 10, 12, 0.81, 3, precision, seed=7, svd_tol=1e-6,
+                                   schedule=schedule)
     assert P.rank < 10
     assert rel_linf(Q, Qref) <= TOL[precision]
 
@@ -158,3 +162,38 @@ def test_dg1d_full_size_sampled_items():
         plan.conserve(Q)
         Qc = Q.cpu().numpy()
         assert np.all(oc.conservation_residual(Qc, N, L) <= 1e-12)
+
+
+@pytest.mark.parametrize("N,L,N_rho,M,batch", [(8, 4.0, 4, 6, 9), (12, 5.0, 6, 12, 5),
+                                               (16, 6.0, 8, 12, 3), (24, 6.0, 12, 12, 2),
+                                               (32, 6.0, 6, 6, 2)])
+def test_fused_gain_schedule_matches_oracle_and_two_pass(N, L, N_rho, M, batch):
+    """FP32 single-pass gain kernel (schedule 2) against the oracle and the
+    two-pass schedule on the same inputs."""
+    print(f"case fused N={N} batch={batch}", flush=True)
+    sph = W.sphere_rule(M)
+    f = W.maxwellian_mixture(batch, N, L, 300 + N)
+    P = spectral.Params(N, L, N_rho, sph[0], sph[1], 0.81)
+    plan = qc.Plan(N, L, N_rho, sphere=sph, omega=0.81, precision=qc.QCOLL_FP32)
+    fg = gpu(f)
+    plan.set_schedule(2)
+    Qf = plan.eval(fg).cpu().numpy()
+    plan.set_schedule(1)
+    Qt = plan.eval(fg).cpu().numpy()
+    Qref = spectral.collide_batch(f, P)
+    e_f, e_t = rel_linf(Qf, Qref), rel_linf(Qt, Qref)
+    print(f"fused {e_f:.3e} two-pass {e_t:.3e}", flush=True)
+    assert e_f <= TOL[qc.QCOLL_FP32]
+    assert rel_linf(Qf, Qt) <= 2 * TOL[qc.QCOLL_FP32]
+
+
+def test_schedule_requests_are_validated():
+    plan = qc.Plan(48, 9.0, 2, sphere=None, omega=0.81, precision=qc.QCOLL_FP32)
+    with pytest.raises(qc.QcollError) as e:
+        plan.set_schedule(2)
+    assert e.value.code == 2
+    plan64 = qc.Plan(16, 6.0, 2, sphere=None, omega=0.81, precision=qc.QCOLL_FP64)
+    with pytest.raises(qc.QcollError):
+        plan64.set_schedule(2)
+    with pytest.raises(qc.QcollError):
+        plan64.set_schedule(5)
