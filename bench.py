@@ -12,6 +12,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-acc]
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -24,6 +25,8 @@ sys.path.insert(0, ROOT)
 METRIC = "Q(f,f) evals/sec at N=32^3,M=12,Nρ=16: FP32+fix vs FP64, at rel L∞ err"
 WORKLOAD = "dg1d_32"
 HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK = 157.3        # TFLOP/s, published (packed FP32)
+FP32_VALU_NONPACKED = 78.6    # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 
 
 def _oracle_item(args):
@@ -56,6 +59,85 @@ def cpu_baseline(f, prm, n_items):
                       f"{dt:.1f} s wall on {min(cores, n)} processes"}, dict(res)
 
 
+def model_flops_per_term(N):
+    """Model flops of one (item, rho_p, sigma_q) term of the hot loop: one complex
+    3-D transform (5 n log2 n with n = N^3) plus the multiplier, the product and
+    the accumulation (10 flops per point)."""
+    n3 = N ** 3
+    return 5.0 * n3 * math.log2(n3) + 10.0 * n3
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    if the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    ent = d.get(kernel)
+    if not ent or ent.get("source_sha256") != source_digest(ent.get("sources", [])):
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def source_digest(files):
+    """sha256 over the named kernel sources (the counters go stale when they change)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1809_10186_amd", "csrc")
+    for fn in files:
+        with open(os.path.join(csrc, fn), "rb") as fh:
+            h.update(fn.encode() + fh.read())
+    return h.hexdigest()
+
+
+def roofline(name, tot_ms, launches, steps, B, N, Nr, M):
+    """Roofline entry of the dominant kernel.  Units per launch are explained in
+    DESIGN.md (section "Kernels and their rooflines")."""
+    n3 = N ** 3
+    avg_ms = tot_ms / launches
+    base = {"kernel": name, "avg_launch_ms": round(avg_ms, 4), "launches": launches,
+            "traffic": measured_traffic(name)}
+    if name == "gain fused":
+        # ALU bound: model flops of every (item, p, q) term of the timed region
+        flops = B * Nr * M * steps * model_flops_per_term(N)
+        per_launch = flops / launches
+        achieved = per_launch / (avg_ms * 1e-3) / 1e12
+        base.update({"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_VALU_PEAK,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP32_VALU_PEAK, 4),
+                     "flops_per_launch": per_launch,
+                     "peak_nonpacked_fp32": FP32_VALU_NONPACKED})
+        return base
+    es = 4
+    if name == "gain slab":        # 8 B in + 8 B out per point per (item, p, q) task
+        total = 2 * 2 * es * n3 * B * Nr * M * steps
+    elif name == "gain pencil":    # 8 M B in + 4 B out per point per (item, p) pair
+        total = (2 * es * n3 * M + es * n3) * B * Nr * steps
+    else:
+        total = None
+    if total is None:
+        base.update({"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None})
+        return base
+    per_launch = total / launches
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    base.update({"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_launch": per_launch})
+    return base
+
+
+def copy_probe(mib=1024, reps=5):
+    """A plain device copy of known size, for calibrating the HBM byte counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "reps": reps}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,7 +147,11 @@ def main():
     ap.add_argument("--no-acc", action="store_true")
     ap.add_argument("--cpu-items", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=0, help="hot-loop schedule of the FP32 plan (0 auto)")
+    ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter calibration)")
     a = ap.parse_args()
+    if a.copy_probe:
+        copy_probe()
+        return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: every item is independent and the box has one GPU; "
               "run with --gpus 1", file=sys.stderr)
@@ -119,36 +205,11 @@ def main():
     del stream
 
     # roofline of the dominant kernel (largest summed duration) of the FP32 step
-    dom = max(kt32.items(), key=lambda kv: kv[1][0])
-    name, (tot_ms, launches) = dom
+    name, (tot_ms, launches) = max(kt32.items(), key=lambda kv: kv[1][0])
     info = plans[qc.QCOLL_FP32].info()
-    n3 = N ** 3
-    es = 4  # FP32 complex parts
-    Nr, M = w["N_rho"], w["M"]
-    # algorithmic bytes of the whole timed region for the pass-structured hot
-    # loop ("Roofline accounting"):
-    #   gain slab  : per (item, p, q) task, read the spectrum and write one
-    #                complex volume: 2 * 8 B per point (FP32 complex);
-    #   gain pencil: per (item, p) pair, read M complex volumes, write A_p:
-    #                (8 M + 4) B per point.
-    if name == "gain slab":
-        total_bytes = 2 * 2 * es * n3 * B * Nr * M * a.steps
-    elif name == "gain pencil":
-        total_bytes = (2 * es * n3 * M + es * n3) * B * Nr * a.steps
-    else:
-        total_bytes = None
-    avg_ms = tot_ms / launches
-    if total_bytes is not None:
-        bytes_per_launch = total_bytes / launches
-        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-        roof = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "avg_launch_ms": round(avg_ms, 4), "launches": launches,
-                "bytes_per_launch": bytes_per_launch}
-    else:
-        roof = {"kernel": name, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": None, "traffic": None, "avg_launch_ms": round(avg_ms, 4), "launches": launches}
+    roof = roofline(name, tot_ms, launches, a.steps, B, N, w["N_rho"], w["M"])
     kernel_ms = {k: round(v[0] / a.steps, 4) for k, v in kt32.items()}
+    Nr, M = w["N_rho"], w["M"]
 
     acc = None
     cpu = None

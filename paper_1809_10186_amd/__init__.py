@@ -262,3 +262,36 @@ def timing_read():
         _check(lib().qcoll_timing_read(name.encode(), ctypes.byref(ms), ctypes.byref(n)))
         out[name] = (ms.value, n.value)
     return out
+
+
+def collide(f, plan, omega=None, conserve=True):
+    """Differentiable Q(f,f) (optionally conservation-projected).
+
+    f: float64 CUDA tensor [..., N, N, N].  omega: optional 0-d float64 tensor;
+    when given (requires_grad allowed) the plan's omega is set to its value and
+    its gradient is sum over the batch of g . dQ/d omega.  The backward pass
+    calls qcoll_vjp (through the projection when conserve is True).
+    """
+    import torch
+
+    class _Collide(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, f_, om_):
+            if om_ is not None and abs(float(om_) - plan.info()["omega"]) > 0:
+                plan.set_omega(float(om_))
+            Q = plan.eval(f_.contiguous())
+            if conserve:
+                plan.conserve(Q)
+            ctx.save_for_backward(f_)
+            return Q
+
+        @staticmethod
+        def backward(ctx, gQ):
+            (f_,) = ctx.saved_tensors
+            want_f = ctx.needs_input_grad[0]
+            want_w = len(ctx.needs_input_grad) > 1 and ctx.needs_input_grad[1]
+            df, dw = plan.vjp(f_.contiguous(), gQ.contiguous(), through_conserve=conserve,
+                              want_df=want_f, want_domega=want_w)
+            return (df if want_f else None), (dw.sum().reshape(()) if want_w else None)
+
+    return _Collide.apply(f, omega)

@@ -212,10 +212,14 @@ qcoll_status qcoll_vjp(qcoll_plan plan, int64_t batch, const double *f, const do
     return fail(QCOLL_ENOTSUP, "the omega gradient needs an untruncated plan (svd_rank < 0)");
   const qcoll::Layout lay = qcoll::make_layout(plan->p, batch, 1);
   if (!ws || ws_bytes < lay.total) return fail(QCOLL_EWORKSPACE, "workspace missing or smaller than qcoll_workspace_bytes");
+  const long n3 = plan->p.n3();
+  if (df && (((const void *)df < (const void *)(f + batch * n3) && (const void *)f < (const void *)(df + batch * n3)) ||
+             ((const void *)df < (const void *)(g + batch * n3) && (const void *)g < (const void *)(df + batch * n3))))
+    return fail(QCOLL_EINVAL, "df must not overlap f or g");
   qcoll_status st = check_device(plan->p);
   if (st != QCOLL_OK) return st;
-  (void)through_conserve;
-  return fail(QCOLL_ENOTSUP, "qcoll_vjp is not available in this build");
+  return qcoll::launch_vjp(plan->p, batch, f, g, df, domega, through_conserve != 0, ws, lay,
+                           static_cast<hipStream_t>(stream));
 }
 
 qcoll_status qcoll_poll(qcoll_plan plan) {

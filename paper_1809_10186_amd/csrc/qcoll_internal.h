@@ -45,7 +45,7 @@ struct Plan {
 // workspace layout for one call; sizes in bytes, offsets 256-aligned
 struct Layout {
   long bc = 0;          // items per chunk
-  long pc = 0;          // (item, radial node) pairs per hot-loop launch
+  long pc = 0;          // eval: (item, radial node) pairs per hot-loop launch; vjp: items per sub-chunk
   size_t off_h = 0, off_h64 = 0, off_a = 0, off_b = 0, off_w = 0, off_t = 0, off_l = 0, off_y = 0;
   size_t off_g = 0, off_z = 0, off_hp = 0, off_d = 0;  // vjp extras
   size_t total = 0;
@@ -61,7 +61,8 @@ qcoll_status launch_project(const Plan &p, int64_t batch, const double *in, doub
 qcoll_status launch_moments(const Plan &p, int64_t batch, const double *f, double *out,
                             hipStream_t st);
 qcoll_status launch_vjp(const Plan &p, int64_t batch, const double *f, const double *g,
-                        double *df, double *domega, void *ws, const Layout &lay, hipStream_t st);
+                        double *df, double *domega, bool through_conserve, void *ws, const Layout &lay,
+                        hipStream_t st);
 
 bool supported_N(int N);
 bool fused_gain_supported(int N, int precision);

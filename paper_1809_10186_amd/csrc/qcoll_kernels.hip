@@ -375,11 +375,33 @@ Layout make_layout(const Plan &p, int64_t batch, int op) {
   Layout l;
   const size_t es = (p.precision == QCOLL_FP32) ? sizeof(float) : sizeof(double);
   const long n3 = p.n3();
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  size_t o = 0;
+  if (op == 1) {
+    // vjp: items per chunk and per gain sub-chunk (Y holds N_rho*M complex volumes per item)
+    l.bc = batch < 32 ? (batch > 0 ? batch : 1) : 32;
+    const size_t per_item_y = size_t(p.N_rho) * p.M * n3 * 2 * es;
+    long pc = long((size_t(200) << 20) / per_item_y);
+    l.pc = pc < 1 ? 1 : (pc > l.bc ? l.bc : pc);
+    const size_t c64 = size_t(l.bc) * n3 * 2 * sizeof(double), cT = size_t(l.bc) * n3 * 2 * es;
+    l.off_h64 = o; o += al(c64);
+    l.off_g = o; o += al(c64);
+    l.off_z = o; o += al(c64);
+    l.off_h = o; o += al(cT);
+    l.off_w = o; o += al(cT);
+    l.off_b = o; o += al(size_t(l.bc) * p.npair() * n3 * 2 * es);
+    l.off_hp = o; o += al(size_t(l.bc) * p.N_rho * n3 * es);
+    l.off_y = o; o += al(size_t(l.pc) * per_item_y);
+    l.off_t = o; o += al(cT);
+    l.off_l = o; o += al(c64);
+    l.off_a = o; o += al(size_t(l.bc) * n3 * sizeof(double));
+    l.off_d = o; o += al(size_t(l.bc) * p.N_rho * sizeof(double));
+    l.total = o;
+    return l;
+  }
   l.bc = batch < 64 ? (batch > 0 ? batch : 1) : 64;
   l.pc = 128;
   if (l.pc > l.bc * p.N_rho) l.pc = l.bc * p.N_rho;
-  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  size_t o = 0;
   l.off_h = o; o += al(size_t(l.bc) * n3 * 2 * es);
   l.off_h64 = l.off_h;
   if (p.precision == QCOLL_FP32) { l.off_h64 = o; o += al(size_t(l.bc) * n3 * 2 * sizeof(double)); }
@@ -389,7 +411,6 @@ Layout make_layout(const Plan &p, int64_t batch, int op) {
   l.off_t = o; o += al(size_t(l.bc) * n3 * 2 * es);
   l.off_l = o; o += al(size_t(l.bc) * n3 * 2 * sizeof(double));
   l.off_y = o; o += use_fused_gain(p) ? 0 : al(size_t(l.pc) * p.M * n3 * 2 * es);
-  (void)op;
   l.total = o;
   return l;
 }

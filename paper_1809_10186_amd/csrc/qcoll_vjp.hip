@@ -1,0 +1,420 @@
+// Vector-Jacobian product of Q(f,f) with respect to f and omega.
+//
+// With u_pq = ifft3[c_s fft3 f] (the same transform as the forward hot loop),
+// h_p = C_p g (multiplier alpha_p, or its truncation) and the loss multiplier
+// Lam:
+//   J^T g = 2 Re ifft3[ sum_pq w_q c_s fft3( h_p conj(u_pq) ) ]
+//           - g * ifft3[Lam fft3 f] - ifft3[Lam fft3(f g)],
+// which follows from the forward form Q = sum_p C_p sum_q w_q t1 t2 - f Lam~ f
+// with t1 + i t2 = (1 + i) u, the adjoint of a shift being the opposite shift
+// and C_p, Lam~ self-adjoint.  omega enters through b(omega) rho_p^{4-2 omega}:
+//   g . dQ/d omega = sum_p dlog_p ( <h_p, A_p> - <f g, Lam~_p f> ),
+// A_p = sum_q w_q t1 t2, and the loss part is a Fourier-space dot product.
+//
+// Passes per (item, p, q): the forward slab pass of the hot loop, a pencil pass
+// that inverts along axis 1, forms w_q h_p conj(u), accumulates <h_p, A_p> and
+// transforms back along axis 1, and a slab pass that transforms the two inner
+// axes forward and accumulates c_s * (.) for every (p, q) of the item.
+#include <hip/hip_runtime.h>
+
+#include "qcoll_passes.hpp"
+
+namespace qcoll {
+
+// f * g as a complex FP64 volume, slab g = item*N + j1
+template <int N>
+struct SrcProd {
+  const double *f, *g;
+  __device__ C<double> operator()(long s, int r, int c) const {
+    const long o = (s * N + r) * N + c;
+    return C<double>{f[o] * g[o], 0.0};
+  }
+};
+
+// (V_2s + i V_2s+1) * G^ for pair s of item b, slab = (b*npair + s)*N + k1
+template <typename T, int N>
+struct SrcVPair {
+  const C<T> *G;
+  const T *V;
+  int npair;
+  __device__ C<T> operator()(long g, int r, int c) const {
+    constexpr long n3 = long(N) * N * N;
+    const long t = g / N;
+    const int k1 = int(g % N);
+    const long b = t / npair;
+    const int s = int(t % npair);
+    const long o = (long(k1) * N + r) * N + c;
+    const C<T> x = G[b * n3 + o];
+    const T a = V[(2 * s) * n3 + o], d = V[(2 * s + 1) * n3 + o];
+    return C<T>{x.re * a - x.im * d, x.re * d + x.im * a};
+  }
+};
+
+// h_p = sum_s U[s][p] R_s, R_s = Re/Im of the packed pair buffer
+template <typename T>
+__global__ void k_unpack_mix(const C<T> *R, const T *U, T *Hp, long nitems, int S, int Nr, int npair, long n3) {
+  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nitems * n3) return;
+  const long b = i / n3, j = i % n3;
+  T rv[64];
+  for (int s = 0; s < S; ++s) {
+    const C<T> x = R[(b * npair + s / 2) * n3 + j];
+    rv[s] = (s % 2 == 0) ? x.re : x.im;
+  }
+  for (int p = 0; p < Nr; ++p) {
+    T acc = T(0);
+    for (int s = 0; s < S; ++s) acc += U[s * Nr + p] * rv[s];
+    Hp[(b * Nr + p) * n3 + j] = acc;
+  }
+}
+
+// adjoint pencil pass: per (item, p) pair and pencil (j2, j3), for every q:
+// u = inverse along axis 1; y = w_q h_p conj(u); <h_p, w_q t1 t2> accumulated;
+// y transformed forward along axis 1 and stored back in place.
+template <typename T, int N>
+struct OpAdjPencil {
+  C<T> *Y;
+  const T *Hp;
+  const T *wq;
+  double *dwg;     // [pairs] accumulators of <h_p, A_p>, or null
+  long bp0;        // first (item, p) pair of this launch (within the chunk)
+  int M;
+  __device__ void operator()(long bpl, int r) const {
+    constexpr long n2 = long(N) * N, n3 = n2 * N;
+    const T *h = Hp + (bp0 + bpl) * n3 + r;
+    T hv[N];
+    static_for<0, N>([&](auto j) { hv[decltype(j)::value] = h[decltype(j)::value * n2]; });
+    double dot = 0.0;
+    for (int q = 0; q < M; ++q) {
+      C<T> *y = Y + (bpl * M + q) * n3 + r;
+      T xr[N], xi[N];
+      static_for<0, N>([&](auto k) {
+        const C<T> v = y[decltype(k)::value * n2];
+        xr[decltype(k)::value] = v.re;
+        xi[decltype(k)::value] = v.im;
+      });
+      fft_reg<N, +1, T>(xr, xi);
+      const T w = wq[q];
+      T part = T(0);
+      static_for<0, N>([&](auto j) {
+        constexpr int jj = decltype(j)::value;
+        part += hv[jj] * (xr[jj] * xr[jj] - xi[jj] * xi[jj]);
+        const T s = w * hv[jj];
+        xr[jj] = s * xr[jj];
+        xi[jj] = -s * xi[jj];
+      });
+      dot += double(w) * double(part);
+      fft_reg<N, -1, T>(xr, xi);
+      static_for<0, N>([&](auto k) { y[decltype(k)::value * n2] = C<T>{xr[decltype(k)::value], xi[decltype(k)::value]}; });
+    }
+    if (dwg) atomicAdd(dwg + bp0 + bpl, dot);
+  }
+};
+
+// adjoint accumulation: Z[b] slab k1 = sum_{p,q} c_s(k) * fft2d(Y_(b,p,q) slab k1)
+// over the items [ib0, ib0 + ni) of the sub-chunk; one workgroup owns SPB slabs
+// of Z (possibly of two items) and loops over all N_rho*M tasks of each.
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_adj_acc(const C<T> *Y, const C<T> *phase, C<T> *Z, long ib0, long ni,
+                                                 int M, int Nr) {
+  constexpr int SPB = spb<T, N>();
+  constexpr long n2 = long(N) * N, n3 = n2 * N;
+  __shared__ T sre[SPB][N][N + 1];
+  __shared__ T sim[SPB][N][N + 1];
+  const long z0 = long(blockIdx.x) * SPB;   // first Z slab (relative to ib0)
+  const long nz = ni * N;
+  T ar[N], ai[N];
+  static_for<0, N>([&](auto k) { ar[decltype(k)::value] = T(0); ai[decltype(k)::value] = T(0); });
+  const int ntask = Nr * M;
+  for (int task = 0; task < ntask; ++task) {
+    const int p = task / M, q = task % M;
+    for (int e = threadIdx.x; e < SPB * N * N; e += SPB * N) {
+      const int s = e / (N * N), rc = e % (N * N), r = rc / N, c = rc % N;
+      const long z = z0 + s;
+      C<T> v{T(0), T(0)};
+      if (z < nz) {
+        const long bl = z / N;
+        const int k1 = int(z % N);
+        v = Y[((bl * Nr + p) * M + q) * n3 + (long(k1) * N + r) * N + c];
+      }
+      sre[s][r][c] = v.re;
+      sim[s][r][c] = v.im;
+    }
+    __syncthreads();
+    lds_slab_fft<T, N, SPB, -1>(sre, sim);
+    const C<T> *ph = phase + size_t(p * M + q) * 3 * N;
+    static_for<0, N>([&](auto kk) {
+      const int e = threadIdx.x + decltype(kk)::value * (SPB * N);
+      const int s = e / (N * N), rc = e % (N * N), r = rc / N, c = rc % N;
+      const int k1 = int((z0 + s) % N);
+      const C<T> b1 = ph[k1], b2 = ph[N + r], b3 = ph[2 * N + c];
+      const T x12 = b1.re * b2.re - b1.im * b2.im, y12 = b1.re * b2.im + b1.im * b2.re;
+      const T cm = (x12 * b3.re - y12 * b3.im) + (x12 * b3.im + y12 * b3.re);
+      ar[decltype(kk)::value] += cm * sre[s][r][c];
+      ai[decltype(kk)::value] += cm * sim[s][r][c];
+    });
+    __syncthreads();
+  }
+  static_for<0, N>([&](auto kk) {
+    const int e = threadIdx.x + decltype(kk)::value * (SPB * N);
+    const int s = e / (N * N), rc = e % (N * N), r = rc / N, c = rc % N;
+    const long z = z0 + s;
+    if (z < nz) {
+      const long bl = z / N;
+      const int k1 = int(z % N);
+      Z[(ib0 + bl) * n3 + (long(k1) * N + r) * N + c] = C<T>{ar[decltype(kk)::value], ai[decltype(kk)::value]};
+    }
+  });
+}
+
+// loss adjoint spectrum, FP64: Lam (H + i FG), slab = item*N + k1
+template <int N>
+struct SrcLossAdj {
+  const C<double> *H, *FG;
+  const double *lam;
+  __device__ C<double> operator()(long g, int r, int c) const {
+    const long o = (g * N + r) * N + c;
+    const double l = lam[((g % N) * N + r) * N + c];
+    const C<double> h = H[o], x = FG[o];
+    return C<double>{(h.re - x.im) * l, (h.im + x.re) * l};
+  }
+};
+
+// final pencil pass: df = 2 Re ifft(Z)/N^3 - g Re(L) - Im(L)
+template <typename T, int N>
+struct OpVjpAssemble {
+  const C<T> *Z;
+  const C<double> *Lm;
+  const double *g;
+  double *df;
+  __device__ void operator()(long b, int r) const {
+    constexpr long n2 = long(N) * N, n3 = n2 * N;
+    double out[N];
+    {
+      T zr[N], zi[N];
+      const C<T> *x = Z + b * n3 + r;
+      static_for<0, N>([&](auto k) {
+        const C<T> v = x[decltype(k)::value * n2];
+        zr[decltype(k)::value] = v.re;
+        zi[decltype(k)::value] = v.im;
+      });
+      fft_reg<N, +1, T>(zr, zi);
+      constexpr double sc = 2.0 / double(n3);
+      static_for<0, N>([&](auto j) { out[decltype(j)::value] = sc * double(zr[decltype(j)::value]); });
+    }
+    {
+      double lr[N], li[N];
+      const C<double> *x = Lm + b * n3 + r;
+      static_for<0, N>([&](auto k) {
+        const C<double> v = x[decltype(k)::value * n2];
+        lr[decltype(k)::value] = v.re;
+        li[decltype(k)::value] = v.im;
+      });
+      fft_reg<N, +1, double>(lr, li);
+      const double *gb = g + b * n3 + r;
+      static_for<0, N>([&](auto j) {
+        constexpr int jj = decltype(j)::value;
+        out[jj] -= gb[jj * n2] * lr[jj] + li[jj];
+      });
+    }
+    double *o = df + b * n3 + r;
+    static_for<0, N>([&](auto j) { o[decltype(j)::value * n2] = out[decltype(j)::value]; });
+  }
+};
+
+// loss part of the omega gradient and the final combination, one workgroup per item:
+// domega[b] = sum_p dlog_p ( dwg[b][p] - (1/N^3) sum_k Re(conj(FG) H) Lam_p(k) )
+__global__ __launch_bounds__(256) void k_domega(const C<double> *H, const C<double> *FG, const double *lam_p,
+                                                const double *dlog, const double *dwg, double *domega, int Nr,
+                                                long n3) {
+  const long b = blockIdx.x;
+  __shared__ double red[256];
+  double tot = 0.0;
+  for (int p = 0; p < Nr; ++p) {
+    double s = 0.0;
+    for (long k = threadIdx.x; k < n3; k += blockDim.x) {
+      const C<double> h = H[b * n3 + k], x = FG[b * n3 + k];
+      s += (x.re * h.re + x.im * h.im) * lam_p[p * n3 + k];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+      if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    tot += dlog[p] * (dwg[b * Nr + p] - red[0] / double(n3));
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) domega[b] = tot;
+}
+
+// out = P in (conservation projection, out of place), one workgroup per item
+__global__ __launch_bounds__(256) void k_project(const double *in, double *out, const double *ginv, int N,
+                                                 double L) {
+  const long n3 = long(N) * N * N;
+  const long b = blockIdx.x;
+  const double *x = in + b * n3;
+  double *y = out + b * n3;
+  const double dc = 2.0 * L / N;
+  double s[5] = {0, 0, 0, 0, 0};
+  for (long j = threadIdx.x; j < n3; j += blockDim.x) {
+    const int i1 = int(j / (N * N)), i2 = int((j / N) % N), i3 = int(j % N);
+    const double c1 = -L + (i1 + 0.5) * dc, c2 = -L + (i2 + 0.5) * dc, c3 = -L + (i3 + 0.5) * dc;
+    const double v = x[j];
+    s[0] += v;
+    s[1] += v * c1;
+    s[2] += v * c2;
+    s[3] += v * c3;
+    s[4] += v * (c1 * c1 + c2 * c2 + c3 * c3);
+  }
+  __shared__ double red[5][256];
+  for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = s[k];
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w)
+      for (int k = 0; k < 5; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  double lam[5];
+  for (int a = 0; a < 5; ++a) {
+    double acc = 0;
+    for (int c = 0; c < 5; ++c) acc += ginv[a * 5 + c] * red[c][0];
+    lam[a] = acc;
+  }
+  for (long j = threadIdx.x; j < n3; j += blockDim.x) {
+    const int i1 = int(j / (N * N)), i2 = int((j / N) % N), i3 = int(j % N);
+    const double c1 = -L + (i1 + 0.5) * dc, c2 = -L + (i2 + 0.5) * dc, c3 = -L + (i3 + 0.5) * dc;
+    y[j] = x[j] - (lam[0] + lam[1] * c1 + lam[2] * c2 + lam[3] * c3 + lam[4] * (c1 * c1 + c2 * c2 + c3 * c3));
+  }
+}
+
+__global__ void k_fill(double *p, long n, double v) {
+  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <typename T, int N>
+struct Vjp {
+  using P = Passes<T, N>;
+  using P64 = Passes<double, N>;
+  static constexpr long n3 = P::n3;
+  static constexpr int SPB = spb<T, N>();
+
+  static qcoll_status run(const Plan &p, int64_t batch, const double *f, const double *g_in, double *df,
+                          double *domega, bool through, void *ws, const Layout &lay, hipStream_t st) {
+    char *w = static_cast<char *>(ws);
+    C<double> *H64 = reinterpret_cast<C<double> *>(w + lay.off_h64);
+    C<double> *G64 = reinterpret_cast<C<double> *>(w + lay.off_g);
+    C<double> *FG64 = reinterpret_cast<C<double> *>(w + lay.off_z);
+    C<T> *H = reinterpret_cast<C<T> *>(w + lay.off_h);
+    C<T> *GT = reinterpret_cast<C<T> *>(w + lay.off_w);          // spectrum of g in T
+    C<T> *R = reinterpret_cast<C<T> *>(w + lay.off_b);           // packed pair inverses
+    T *Hp = reinterpret_cast<T *>(w + lay.off_hp);
+    C<T> *Y = reinterpret_cast<C<T> *>(w + lay.off_y);
+    C<T> *Z = reinterpret_cast<C<T> *>(w + lay.off_t);
+    C<double> *Lm = reinterpret_cast<C<double> *>(w + lay.off_l);
+    double *gproj = reinterpret_cast<double *>(w + lay.off_a);
+    double *dwg = reinterpret_cast<double *>(w + lay.off_d);
+    const int S = p.rank, np = p.npair(), Nr = p.N_rho, M = p.M;
+    qcoll_status s;
+    for (long b0 = 0; b0 < batch; b0 += lay.bc) {
+      const long nb = (batch - b0 < lay.bc) ? (batch - b0) : lay.bc;
+      const double *fb = f + b0 * n3;
+      const double *gb = g_in + b0 * n3;
+      if (through) {
+        TimedLaunch tl("vjp project", st);
+        hipLaunchKernelGGL(k_project, dim3(unsigned(nb)), dim3(256), 0, st, gb, gproj, p.ginv, N, p.L);
+        QC_LAUNCH_CHECK("vjp project");
+        gb = gproj;
+      }
+      // FP64 spectra of f, g and f g
+      if ((s = P64::forward(fb, H64, nb, st))) return s;
+      if ((s = P64::forward(gb, G64, nb, st))) return s;
+      if ((s = P64::template slab<SrcProd<N>, DstCplx<double, N>, -1>(SrcProd<N>{fb, gb}, DstCplx<double, N>{FG64},
+                                                                    nb * N, st, "vjp fg slab")))
+        return s;
+      if ((s = P64::pencil(OpPencilInPlace<double, N, -1>{FG64}, nb * N * N, st, "vjp fg pencil"))) return s;
+      {
+        TimedLaunch tl("cast", st);
+        hipLaunchKernelGGL(k_cast<T>, dim3(nblk(nb * n3, 256)), dim3(256), 0, st, H64, H, nb * n3);
+        hipLaunchKernelGGL(k_cast<T>, dim3(nblk(nb * n3, 256)), dim3(256), 0, st, G64, GT, nb * n3);
+        QC_LAUNCH_CHECK("cast");
+      }
+      // h_p = C_p g: packed inverse transforms of (V_2s + i V_2s+1) G^, then unpack + mix
+      if ((s = P::template slab<SrcVPair<T, N>, DstCplx<T, N>, +1>(
+               SrcVPair<T, N>{GT, reinterpret_cast<const T *>(p.V), np}, DstCplx<T, N>{R}, nb * np * N, st,
+               "vjp h slab")))
+        return s;
+      if ((s = P::pencil(OpPencilInPlace<T, N, +1>{R}, nb * np * N * N, st, "vjp h pencil"))) return s;
+      {
+        TimedLaunch tl("vjp unpack", st);
+        hipLaunchKernelGGL(k_unpack_mix<T>, dim3(nblk(nb * n3, 256)), dim3(256), 0, st, R,
+                           reinterpret_cast<const T *>(p.umix_d), Hp, nb, S, Nr, np, n3);
+        QC_LAUNCH_CHECK("vjp unpack");
+      }
+      if (domega) {
+        hipLaunchKernelGGL(k_fill, dim3(nblk(nb * Nr, 256)), dim3(256), 0, st, dwg, nb * Nr, 0.0);
+        QC_LAUNCH_CHECK("fill");
+      }
+      // gain adjoint, items in sub-chunks of lay.pc items
+      const T scale = T(1.0 / double(n3));
+      for (long ib0 = 0; ib0 < nb; ib0 += lay.pc) {
+        const long ni = (nb - ib0 < lay.pc) ? (nb - ib0) : lay.pc;
+        const long bp0 = ib0 * Nr;
+        const long cnt = ni * Nr;
+        SrcShift<T, N> src{H, reinterpret_cast<const C<T> *>(p.phase), bp0, M, Nr, scale};
+        if ((s = P::template slab<SrcShift<T, N>, DstCplx<T, N>, +1>(src, DstCplx<T, N>{Y}, cnt * M * N, st,
+                                                                      "vjp gain slab")))
+          return s;
+        OpAdjPencil<T, N> op{Y, Hp, reinterpret_cast<const T *>(p.wq), domega ? dwg : nullptr, bp0, M};
+        if ((s = P::pencil(op, cnt * N * N, st, "vjp gain pencil"))) return s;
+        TimedLaunch tl("vjp gain acc", st);
+        hipLaunchKernelGGL((k_adj_acc<T, N>), dim3(nblk(ni * N, SPB)), dim3(SPB * N), 0, st, Y,
+                           reinterpret_cast<const C<T> *>(p.phase), Z, ib0, ni, M, Nr);
+        QC_LAUNCH_CHECK("vjp gain acc");
+      }
+      // gain inverse (slab pass; the pencil pass is in the assembly)
+      if ((s = P::template slab<SrcCplx<T, N>, DstCplx<T, N>, +1>(SrcCplx<T, N>{Z}, DstCplx<T, N>{Z}, nb * N, st,
+                                                                   "vjp inverse slab")))
+        return s;
+      // loss adjoint spectrum Lam (H + i FG), inverse slab pass
+      if ((s = P64::template slab<SrcLossAdj<N>, DstCplx<double, N>, +1>(
+               SrcLossAdj<N>{H64, FG64, reinterpret_cast<const double *>(p.lam)}, DstCplx<double, N>{Lm}, nb * N,
+               st, "vjp loss slab")))
+        return s;
+      if (df) {
+        if ((s = P::pencil(OpVjpAssemble<T, N>{Z, Lm, gb, df + b0 * n3}, nb * N * N, st, "vjp assemble")))
+          return s;
+      }
+      if (domega) {
+        TimedLaunch tl("vjp domega", st);
+        hipLaunchKernelGGL(k_domega, dim3(unsigned(nb)), dim3(256), 0, st, H64, FG64, p.lam_p, p.dlog, dwg,
+                           domega + b0, Nr, n3);
+        QC_LAUNCH_CHECK("vjp domega");
+      }
+    }
+    return QCOLL_OK;
+  }
+};
+
+template <typename T>
+static qcoll_status vjp_dispatch(const Plan &p, int64_t batch, const double *f, const double *g, double *df,
+                                 double *domega, bool through, void *ws, const Layout &lay, hipStream_t st) {
+  switch (p.N) {
+    case 8: return Vjp<T, 8>::run(p, batch, f, g, df, domega, through, ws, lay, st);
+    case 12: return Vjp<T, 12>::run(p, batch, f, g, df, domega, through, ws, lay, st);
+    case 16: return Vjp<T, 16>::run(p, batch, f, g, df, domega, through, ws, lay, st);
+    case 24: return Vjp<T, 24>::run(p, batch, f, g, df, domega, through, ws, lay, st);
+    case 32: return Vjp<T, 32>::run(p, batch, f, g, df, domega, through, ws, lay, st);
+    case 48: return Vjp<T, 48>::run(p, batch, f, g, df, domega, through, ws, lay, st);
+    default: set_error("unsupported N"); return QCOLL_ENOTSUP;
+  }
+}
+
+qcoll_status launch_vjp(const Plan &p, int64_t batch, const double *f, const double *g, double *df,
+                        double *domega, bool through, void *ws, const Layout &lay, hipStream_t st) {
+  if (p.precision == QCOLL_FP32) return vjp_dispatch<float>(p, batch, f, g, df, domega, through, ws, lay, st);
+  return vjp_dispatch<double>(p, batch, f, g, df, domega, through, ws, lay, st);
+}
+
+}  // namespace qcoll
