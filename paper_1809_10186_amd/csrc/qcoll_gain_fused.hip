@@ -4,7 +4,9 @@
 // For each half-sphere point q the kernel forms u = ifft3[c_s * H] with the
 // real shift multiplier c_s = Re beta_s + Im beta_s (s = rho_p sigma_q / 2) and
 // accumulates A_p += w_q (Re(u)^2 - Im(u)^2) = w_q t1 t2 (Appendix, the
-// product of the two shifted copies of f for one quadrature term).
+// product of the two shifted copies of f for one quadrature term).  It then
+// applies the low-rank weight on chip: W_p = alpha_p(k) * fft3(A_p), so that
+// the gain spectrum is the sum over p of W_p.
 //
 // Layout: the workgroup has N^2 lanes, one pencil each.
 //   stage A  lane (k2, k3): pencil along axis 1, loaded straight from H with
@@ -13,6 +15,8 @@
 //   stage B  lane (j1, k3): pencil along axis 2 after an LDS transpose;
 //   stage C  lane (j1, j2): pencil along axis 3 after a second transpose;
 //            the lane owns A_p[j1][j2][:] in registers across all q.
+// The forward transform of A_p runs the same stages backwards and stores
+// W_p[k1][k2][k3] from lane (k2, k3), coalesced.
 // Each transpose moves the real parts, then the imaginary parts, through one
 // LDS tile of N * (N^2 + 32) floats (135 KiB at N = 32).  The padding makes
 // both the writes and the reads of each transpose free of bank conflicts at
@@ -68,8 +72,9 @@ template <int N>
 __global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<float> *__restrict__ H,
                                                                  const cplx<float> *__restrict__ phase,
                                                                  const float *__restrict__ wq,
-                                                                 float *__restrict__ A, long nbp, int M, int Nr,
-                                                                 float scale) {
+                                                                 const float *__restrict__ alpha_eff,
+                                                                 cplx<float> *__restrict__ W, long nbp, int M,
+                                                                 int Nr, float scale) {
   using G = FusedGeom<N>;
   constexpr int PPL = G::PPL, NL = G::NL;
   constexpr long n2 = long(N) * N, n3 = n2 * N;
@@ -143,16 +148,46 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<floa
       });
     });
   }
-  // lane (j1, j2) owns the row A_p[j1][j2][:]
-  static_for<0, PPL>([&](auto uu) {
-    constexpr int u = decltype(uu)::value;
-    float *a = A + bp * n3 + long(lane + u * NL) * N;
-    static_for<0, N>([&](auto j) { a[decltype(j)::value] = acc[u][decltype(j)::value]; });
-  });
+  // Low-rank stage on chip: forward 3-D transform of the real A_p (the same
+  // two transposes, run backwards), times the gain weights alpha_p(k) (or
+  // their truncation, already / N^3), stored as the spectrum W[item][p].
+  // lane (j1, j2): axis 3; lane (j1, k3): axis 2; lane (k2, k3): axis 1.
+  {
+    float zr[PPL][N], zi[PPL][N];
+    static_for<0, PPL>([&](auto uu) {
+      constexpr int u = decltype(uu)::value;
+      static_for<0, N>([&](auto j) {
+        zr[u][decltype(j)::value] = acc[u][decltype(j)::value];
+        zi[u][decltype(j)::value] = 0.f;
+      });
+      fft_reg<N, -1, float>(zr[u], zi[u]);
+    });
+    auto wa1 = [&](int u, int i) { return i * S1 + hi[u] * N + lo[u]; };
+    auto ra1 = [&](int u, int i) { return hi[u] * S1 + i * N + lo[u]; };
+    auto wa2 = [&](int u, int i) { return hi[u] * S1 + lo[u] * (N + 1) + i; };
+    auto ra2 = [&](int u, int i) { return hi[u] * S1 + i * (N + 1) + lo[u]; };
+    lds_transpose<N, PPL>(lds, zr, ra2, wa2);
+    lds_transpose<N, PPL>(lds, zi, ra2, wa2);
+    static_for<0, PPL>([&](auto u) { fft_reg<N, -1, float>(zr[decltype(u)::value], zi[decltype(u)::value]); });
+    lds_transpose<N, PPL>(lds, zr, ra1, wa1);
+    lds_transpose<N, PPL>(lds, zi, ra1, wa1);
+    const float *ae = alpha_eff + long(p) * n3;
+    cplx<float> *wout = W + bp * n3;
+    static_for<0, PPL>([&](auto uu) {
+      constexpr int u = decltype(uu)::value;
+      fft_reg<N, -1, float>(zr[u], zi[u]);
+      static_for<0, N>([&](auto k) {
+        constexpr int kk = decltype(k)::value;
+        const long o = kk * n2 + lane + u * NL;
+        const float a = ae[o];
+        wout[o] = cplx<float>{zr[u][kk] * a, zi[u][kk] * a};
+      });
+    });
+  }
 }
 
 template <int N>
-static qcoll_status launch_fused(const Plan &p, const cplx<float> *H, float *A, long nbp, hipStream_t st) {
+static qcoll_status launch_fused(const Plan &p, const cplx<float> *H, cplx<float> *W, long nbp, hipStream_t st) {
   using G = FusedGeom<N>;
   // the LDS tile exceeds the default dynamic limit at N = 32; set per call
   // (cheap) so that every device the process uses gets the attribute
@@ -164,8 +199,8 @@ static qcoll_status launch_fused(const Plan &p, const cplx<float> *H, float *A, 
   TimedLaunch tl("gain fused", st);
   const float scale = float(1.0 / double(long(N) * N * N));
   hipLaunchKernelGGL(k_gain_fused<N>, dim3(unsigned(nbp)), dim3(G::NL), G::lds_bytes, st, H,
-                     reinterpret_cast<const cplx<float> *>(p.phase), reinterpret_cast<const float *>(p.wq), A,
-                     nbp, p.M, p.N_rho, scale);
+                     reinterpret_cast<const cplx<float> *>(p.phase), reinterpret_cast<const float *>(p.wq),
+                     reinterpret_cast<const float *>(p.alpha_eff), W, nbp, p.M, p.N_rho, scale);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     set_error(std::string("gain fused: ") + hipGetErrorString(e));
@@ -178,9 +213,9 @@ bool fused_gain_supported(int N, int precision) {
   return precision == QCOLL_FP32 && (N == 8 || N == 12 || N == 16 || N == 24 || N == 32);
 }
 
-qcoll_status launch_gain_fused(const Plan &p, const void *H, void *A, long nbp, hipStream_t st) {
+qcoll_status launch_gain_fused(const Plan &p, const void *H, void *W, long nbp, hipStream_t st) {
   const auto *h = static_cast<const cplx<float> *>(H);
-  auto *a = static_cast<float *>(A);
+  auto *a = static_cast<cplx<float> *>(W);
   switch (p.N) {
     case 8: return launch_fused<8>(p, h, a, nbp, st);
     case 12: return launch_fused<12>(p, h, a, nbp, st);

@@ -31,6 +31,7 @@ struct Plan {
   void *wq = nullptr;      // [M] half-sphere weights
   void *V = nullptr;       // [2*npair][N^3] real: spectral factors of the gain / N^3 (zero-padded row)
   void *lam = nullptr;     // [N^3] loss weights / N^3, always FP64
+  void *alpha_eff = nullptr;  // [N_rho][N^3] effective gain weights sum_s U_sp V_s / N^3 (fused schedule)
   void *umix_d = nullptr;  // [rank][N_rho]
   // FP64 device tables
   double *ginv = nullptr;  // [25] (C C^T)^{-1} of the collision invariants on the grid
@@ -67,7 +68,7 @@ qcoll_status launch_vjp(const Plan &p, int64_t batch, const double *f, const dou
 bool supported_N(int N);
 bool fused_gain_supported(int N, int precision);
 bool use_fused_gain(const Plan &p);
-qcoll_status launch_gain_fused(const Plan &p, const void *H, void *A, long nbp, hipStream_t st);
+qcoll_status launch_gain_fused(const Plan &p, const void *H, void *W, long nbp, hipStream_t st);
 
 // kernel timing (hipEvents on the launch stream) for roofline accounting
 bool timing_on();

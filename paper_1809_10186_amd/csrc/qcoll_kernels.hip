@@ -116,6 +116,26 @@ struct OpLowRank {
   }
 };
 
+// fused schedule, gain inverse slab pass: sum over the radial nodes of the
+// per-node gain spectra W[b][p], slab g = item*N + k1
+template <typename T, int N>
+struct SrcSumP {
+  const C<T> *W;
+  int Nr;
+  __device__ C<T> operator()(long g, int r, int c) const {
+    constexpr long n3 = long(N) * N * N;
+    const long b = g / N;
+    const long o = ((g % N) * N + r) * N + c;
+    T re = T(0), im = T(0);
+    for (int p = 0; p < Nr; ++p) {
+      const C<T> v = W[(b * Nr + p) * n3 + o];
+      re += v.re;
+      im += v.im;
+    }
+    return C<T>{re, im};
+  }
+};
+
 // loss, slab pass (FP64): Lambda * H64, slab g = item*N + k1
 template <int N>
 struct SrcLoss {
@@ -189,9 +209,6 @@ struct Engine {
   static qcoll_status gain_terms(const Plan &p, const C<T> *H, T *A, C<T> *Y, long nb, long pc,
                                  hipStream_t st) {
     const long nbp = nb * p.N_rho;
-    if constexpr (std::is_same<T, float>::value) {
-      if (use_fused_gain(p)) return launch_gain_fused(p, H, A, nbp, st);
-    }
     const T scale = T(1.0 / double(n3));
     for (long bp0 = 0; bp0 < nbp; bp0 += pc) {
       const long cnt = (nbp - bp0 < pc) ? (nbp - bp0) : pc;
@@ -227,6 +244,22 @@ struct Engine {
         TimedLaunch tl("cast", st);
         hipLaunchKernelGGL(k_cast<T>, dim3(nblk(nb * n3, 256)), dim3(256), 0, st, H64, H, nb * n3);
         QC_LAUNCH_CHECK("cast");
+      }
+      if constexpr (std::is_same<T, float>::value) {
+        if (use_fused_gain(p)) {
+          // gain terms and the low-rank stage on chip; W[b][p] = alpha_p fft3(A_p)
+          C<T> *Wp = reinterpret_cast<C<T> *>(A);
+          if ((s = launch_gain_fused(p, H, Wp, nb * p.N_rho, st))) return s;
+          if ((s = slab<SrcSumP<T, N>, DstCplx<T, N>, +1>(SrcSumP<T, N>{Wp, p.N_rho}, DstCplx<T, N>{TA}, nb * N, st,
+                                                           "gain inverse slab")))
+            return s;
+          if ((s = Passes<double, N>::template slab<SrcLoss<N>, DstCplx<double, N>, +1>(
+                   SrcLoss<N>{H64, reinterpret_cast<const double *>(p.lam)}, DstCplx<double, N>{LH}, nb * N, st,
+                   "loss slab")))
+            return s;
+          if ((s = pencil(OpAssemble<T, N>{TA, LH, fb, Q + b0 * n3}, nb * N * N, st, "assemble"))) return s;
+          continue;
+        }
       }
       if ((s = gain_terms(p, H, A, Y, nb, lay.pc, st))) return s;
       const T *Bsrc = A;
@@ -405,12 +438,13 @@ Layout make_layout(const Plan &p, int64_t batch, int op) {
   l.off_h = o; o += al(size_t(l.bc) * n3 * 2 * es);
   l.off_h64 = l.off_h;
   if (p.precision == QCOLL_FP32) { l.off_h64 = o; o += al(size_t(l.bc) * n3 * 2 * sizeof(double)); }
-  l.off_a = o; o += al(size_t(l.bc) * p.N_rho * n3 * es);
-  l.off_b = o; o += p.mix_identity ? 0 : al(size_t(l.bc) * p.rank * n3 * es);
-  l.off_w = o; o += al(size_t(l.bc) * p.npair() * n3 * 2 * es);
+  const bool fused = use_fused_gain(p);
+  l.off_a = o; o += al(size_t(l.bc) * p.N_rho * n3 * es * (fused ? 2 : 1));
+  l.off_b = o; o += (p.mix_identity || fused) ? 0 : al(size_t(l.bc) * p.rank * n3 * es);
+  l.off_w = o; o += fused ? 0 : al(size_t(l.bc) * p.npair() * n3 * 2 * es);
   l.off_t = o; o += al(size_t(l.bc) * n3 * 2 * es);
   l.off_l = o; o += al(size_t(l.bc) * n3 * 2 * sizeof(double));
-  l.off_y = o; o += use_fused_gain(p) ? 0 : al(size_t(l.pc) * p.M * n3 * 2 * es);
+  l.off_y = o; o += fused ? 0 : al(size_t(l.pc) * p.M * n3 * 2 * es);
   l.total = o;
   return l;
 }

@@ -158,6 +158,23 @@ static void kernel_tables(const Plan &p, std::vector<double> &alpha, std::vector
       }
 }
 
+// effective per-node gain weights sum_s U[s][p] V_s (already / N^3), for the
+// fused schedule, which transforms each A_p on chip and so cannot mix before
+// the transform
+static qcoll_status upload_alpha_eff(Plan &p, const std::vector<double> &Vs, const std::vector<double> &U) {
+  if (!fused_gain_supported(p.N, p.precision)) return QCOLL_OK;
+  const int m = p.N_rho;
+  const long n3 = p.n3();
+  std::vector<double> ae(size_t(m) * n3, 0.0);
+  for (int s = 0; s < p.rank; ++s)
+    for (int q = 0; q < m; ++q) {
+      const double u = U[size_t(s) * m + q];
+      if (u == 0.0) continue;
+      for (long k = 0; k < n3; ++k) ae[size_t(q) * n3 + k] += u * Vs[size_t(s) * n3 + k];
+    }
+  return p.precision == QCOLL_FP32 ? upload<float>(ae, &p.alpha_eff) : upload<double>(ae, &p.alpha_eff);
+}
+
 static qcoll_status upload_kernel_tables(Plan &p) {
   std::vector<double> alpha, lam, lam_p;
   kernel_tables(p, alpha, lam, lam_p);
@@ -186,6 +203,7 @@ static qcoll_status upload_kernel_tables(Plan &p) {
   if ((st = upload<double>(lams, &p.lam)) != QCOLL_OK) return st;
   if ((st = up(U, &p.umix_d)) != QCOLL_OK) return st;
   p.umix = U;
+  if ((st = upload_alpha_eff(p, Vs, U)) != QCOLL_OK) return st;
   if ((st = upload<double>(lam_p, reinterpret_cast<void **>(&p.lam_p))) != QCOLL_OK) return st;
   std::vector<double> dl(m);
   double dlb = 0.0;
@@ -249,7 +267,7 @@ static qcoll_status upload_truncated(Plan &p, int svd_rank, double svd_tol) {
   if ((st = upload<double>(lams, &p.lam)) != QCOLL_OK) return st;
   if ((st = up(U, &p.umix_d)) != QCOLL_OK) return st;
   p.umix = U;
-  return QCOLL_OK;
+  return upload_alpha_eff(p, Vs, U);
 }
 
 static void free_kernel_tables(Plan &p) {
@@ -258,6 +276,8 @@ static void free_kernel_tables(Plan &p) {
   hipFree(p.umix_d);
   hipFree(p.lam_p);
   hipFree(p.dlog);
+  hipFree(p.alpha_eff);
+  p.alpha_eff = nullptr;
   p.V = p.lam = p.umix_d = nullptr;
   p.lam_p = p.dlog = nullptr;
 }

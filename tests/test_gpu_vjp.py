@@ -101,9 +101,14 @@ def test_adjoint_check_full_size():
     Qp = plan.eval(fg)
     plan.set_omega(om - hw)
     Qm = plan.eval(fg)
-    fd = ((Qp - Qm) / (2 * hw) * gg).sum(dim=(1, 2, 3))
-    err_w = float(((fd - dw).abs() / dw.abs().clamp_min(1e-30)).max())
-    print(f"dot-product rel {err_f:.3e}  omega FD rel {err_w:.3e}", flush=True)
+    dq = (Qp - Qm) / (2 * hw)
+    fd = (dq * gg).sum(dim=(1, 2, 3))
+    # normwise, like the dot-product test: |fd - dw| / sum |g dQ/domega|
+    # (g . dQ/domega itself can nearly cancel for some items)
+    err_w = float(((fd - dw).abs() / (dq * gg).abs().sum(dim=(1, 2, 3))).max())
+    err_plain = float(((fd - dw).abs() / dw.abs().clamp_min(1e-30)).median())
+    print(f"dot-product rel {err_f:.3e}  omega FD normwise {err_w:.3e} (median plain rel {err_plain:.3e})",
+          flush=True)
     assert err_f <= 1e-10
     assert err_w <= 1e-6
     # one item against the oracle's FP64 gradient

@@ -292,3 +292,51 @@ def test_digamma_constant():
     P = params(8, 5.0, 3, omega=0.81)
     dl = P.kt.dlog_c(True) + 2 * np.log(P.kt.rho)
     assert np.allclose(dl, 0.893732, atol=1e-6)
+
+
+# ---------------------------------------------------------------- DG weak form
+def test_dg_triple_tensor_properties():
+    from oracle import dg
+    for P in (1, 2, 3):
+        H = dg.triple_tensor_1d(P)
+        K = P + 1
+        assert H.shape == (K, K, K)
+        # symmetric in all index pairs and sum_m H_{m a b} = mass matrix (partition of unity)
+        assert np.allclose(H, H.transpose(0, 2, 1)) and np.allclose(H, H.transpose(1, 0, 2))
+        nodes, w = dg.gauss_nodes(P)
+        assert np.allclose(H.sum(axis=0), np.diag(w), atol=1e-14)   # Gauss-node Lagrange basis: M = diag(w)
+    H2 = dg.triple_tensor_2d(1)
+    assert H2.shape == (4, 4, 4)
+    assert abs(H2.sum() - 4.0) < 1e-13   # integral of 1 over [-1,1]^2
+
+
+def test_dg_eigen_form_equals_direct_double_sum():
+    """The low-rank (eigen) form of the paper's SVD variant reproduces the
+    direct double sum of the weak form exactly."""
+    from oracle import dg
+    N, L = 8, 5.0
+    P = params(N, L, 4)
+    for deg in (1, 2):
+        H = dg.triple_tensor_1d(deg)
+        K = deg + 1
+        F = W.maxwellian_mixture(K, N, L, 500 + deg, noise=0.2)
+        T, Wm, ranks = dg.eigen_factors(H)
+        assert sum(ranks) <= K * K
+        Cd = dg.collision_term_direct(F, H, P)
+        Cf = dg.collision_term_factored(F, T, Wm, P)
+        assert np.abs(Cd - Cf).max() < 1e-13 * np.abs(Cd).max()
+
+
+def test_dg_collocation_is_q_at_quadrature_points():
+    """With the K-point Gauss rule as quadrature, H_m collapses to w_m e_m e_m^T and
+    the collision term is w_m Q(F_m) (the quadrature-point form)."""
+    from oracle import dg
+    N, L = 8, 5.0
+    P = params(N, L, 4)
+    nodes, w = dg.gauss_nodes(2)
+    ph = dg.lagrange(nodes, nodes)
+    Hq = np.einsum("q,mq,aq,bq->mab", w, ph, ph, ph)
+    F = W.maxwellian_mixture(3, N, L, 600, noise=0.2)
+    C = dg.collision_term_direct(F, Hq, P)
+    ref = np.array([w[m] * spectral.collide(F[m], P) for m in range(3)])
+    assert np.abs(C - ref).max() < 1e-13 * np.abs(ref).max()
