@@ -18,7 +18,8 @@
  *   is a C-order array [N][N][N] of doubles, index (j1, j2, j3) <-> (c1, c2, c3);
  *   a batch is [batch][N][N][N], contiguous.
  * - Pointers named f, g, Q, df, out, moments are DEVICE pointers on the device
- *   the plan was created on, owned by the caller, 8-byte aligned.  Host
+ *   the plan was created on, owned by the caller, 16-byte aligned (an item of
+ *   a batch starts 16-byte aligned whenever the batch does, N being even).  Host
  *   pointers are named as such.  Workspace (ws) is a caller-owned device
  *   buffer of at least qcoll_workspace_bytes() bytes, 256-byte aligned.
  * - stream is a hipStream_t (NULL = the default stream).  Every compute entry
@@ -46,6 +47,7 @@ extern "C" {
 #endif
 
 typedef struct qcoll_plan_s *qcoll_plan;
+typedef struct qcoll_group_s *qcoll_group;
 
 typedef enum {
   QCOLL_OK = 0,
@@ -182,6 +184,61 @@ qcoll_status qcoll_timing_enable(int32_t on);
 qcoll_status qcoll_timing_reset(void);
 qcoll_status qcoll_timing_read(const char *name, double *host_ms, int64_t *host_count);
 qcoll_status qcoll_timing_names(char *host_buf, size_t cap);
+
+/* DG collision term of the weak form (Section 3.4, the collision double sum
+ * and its SVD variant):
+ *   C[e][m] = sum_r W[m][r] Q( sum_l T[r][l] F[e][l] ),   m < K, r < R,
+ * for every element e.  With T the stacked eigenvectors u_{m,r} of the
+ * symmetric triple-tensor slices H_m and W[m][(m,r)] their eigenvalues this
+ * is sum_{l1,l2} H_{m l1 l2} Q(F_l1, F_l2); with T the basis values at
+ * quadrature points and W the weighted basis values it is the quadrature
+ * form.  The two contractions run on MFMA (FP64).
+ *   T: [R][K], W: [K][R] device FP64; F, C: [n_elem][K][N^3] device FP64.
+ *   conserve != 0 applies qcoll_conserve to every Q term before W.
+ * Workspace from qcoll_dg_workspace_bytes (includes the eval workspace). */
+size_t qcoll_dg_workspace_bytes(qcoll_plan plan, int64_t n_elem, int32_t K, int32_t R);
+qcoll_status qcoll_dg_collide(qcoll_plan plan, int64_t n_elem, int32_t K, int32_t R, const double *T,
+                              const double *W, const double *F, double *C, int32_t conserve, void *ws,
+                              size_t ws_bytes, void *stream);
+
+/* Items per chunk of the eval pipeline (0 = default 64); workspace sizes
+ * depend on it.  Results do not. */
+qcoll_status qcoll_plan_set_chunk(qcoll_plan plan, int32_t items);
+
+/* Autotuner: times the candidate schedules of this plan (fused / two-pass hot
+ * loop x 32, 64, 128, 256 items per chunk) with qcoll_eval on the caller's f
+ * and Q (Q is overwritten), keeps the fastest in the plan and returns it in
+ * *host_schedule, *host_chunk (either may be NULL).  Synchronous.  If the
+ * environment variable QCOLL_AUTOTUNE_CACHE names a file, choices are read
+ * from and appended to it, keyed by (arch, N, N_rho, M, precision, rank,
+ * batch rounded up to a power of two). */
+size_t qcoll_autotune_workspace_bytes(qcoll_plan plan, int64_t batch);
+qcoll_status qcoll_autotune(qcoll_plan plan, int64_t batch, const double *f, double *Q, void *ws,
+                            size_t ws_bytes, void *stream, int32_t *host_schedule, int32_t *host_chunk);
+
+/* Groups of plans (several velocity grids / kernels / ranks) with their item
+ * counts, evaluated as one launch: each plan's pipeline runs on its own
+ * stream between a fork and a join on the caller's stream, ordered by model
+ * cost (largest first).  With use_graph != 0 the fork/join is captured into
+ * a hipGraph the first time a given set of pointers is used (stream must not
+ * be the legacy default stream) and replayed with one hipGraphLaunch after
+ * that; the graph holds kernel nodes only.
+ *   plans, counts: HOST arrays of nplans entries (plans outlive the group).
+ *   f, Q, g, df, domega: HOST arrays of nplans DEVICE pointers, entry i laid
+ *   out as for the single-plan calls with counts[i] items (domega may be NULL,
+ *   or have NULL entries).
+ * Workspace from qcoll_group_workspace_bytes(group, op) (op 0 eval, 1 vjp).
+ * Calls on one group must not overlap (they share its streams and graphs). */
+qcoll_status qcoll_group_create(const qcoll_plan *plans, const int64_t *counts, int32_t nplans,
+                                qcoll_group *out);
+qcoll_status qcoll_group_destroy(qcoll_group group);
+size_t qcoll_group_workspace_bytes(qcoll_group group, int32_t op);
+qcoll_status qcoll_group_eval(qcoll_group group, const double *const *f, double *const *Q,
+                              int32_t conserve, void *ws, size_t ws_bytes, void *stream,
+                              int32_t use_graph);
+qcoll_status qcoll_group_vjp(qcoll_group group, const double *const *f, const double *const *g,
+                             double *const *df, double *const *domega, int32_t through_conserve,
+                             void *ws, size_t ws_bytes, void *stream, int32_t use_graph);
 
 /* Synchronise the device, then report and clear the non-finite flag. */
 qcoll_status qcoll_poll(qcoll_plan plan);

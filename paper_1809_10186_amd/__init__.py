@@ -66,6 +66,19 @@ def lib():
             "qcoll_status_str": ([i32], ctypes.c_char_p),
             "qcoll_last_error": ([], ctypes.c_char_p),
             "qcoll_version": ([], i32),
+            "qcoll_dg_workspace_bytes": ([vp, i64, i32, i32], ctypes.c_size_t),
+            "qcoll_dg_collide": ([vp, i64, i32, i32, dp, dp, dp, dp, i32, vp, ctypes.c_size_t, vp], i32),
+            "qcoll_plan_set_chunk": ([vp, i32], i32),
+            "qcoll_autotune_workspace_bytes": ([vp, i64], ctypes.c_size_t),
+            "qcoll_autotune": ([vp, i64, dp, dp, vp, ctypes.c_size_t, vp, ctypes.POINTER(i32),
+                                ctypes.POINTER(i32)], i32),
+            "qcoll_group_create": ([ctypes.POINTER(vp), ctypes.POINTER(i64), i32, ctypes.POINTER(vp)], i32),
+            "qcoll_group_destroy": ([vp], i32),
+            "qcoll_group_workspace_bytes": ([vp, i32], ctypes.c_size_t),
+            "qcoll_group_eval": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp, ctypes.c_size_t, vp, i32],
+                                 i32),
+            "qcoll_group_vjp": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                ctypes.POINTER(vp), i32, vp, ctypes.c_size_t, vp, i32], i32),
             "qcoll_timing_enable": ([i32], i32),
             "qcoll_timing_reset": ([], i32),
             "qcoll_timing_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -239,6 +252,46 @@ class Plan:
                                _ptr(ws), ws.numel(), _stream(stream)))
         return df, domega
 
+    def dg_collide(self, F, T, W, conserve=False, out=None, stream=None):
+        """DG collision term C[e][m] = sum_r W[m][r] Q(sum_l T[r][l] F[e][l]).
+
+        F: float64 [n_elem, K, N, N, N]; T: float64 [R, K]; W: float64 [K, R] (CUDA tensors)."""
+        import torch
+        n = self.N
+        if F.dim() != 5 or F.shape[2:] != (n, n, n) or F.dtype != torch.float64 or not F.is_contiguous():
+            raise ValueError("F must be a contiguous float64 tensor [n_elem, K, N, N, N]")
+        E, K = F.shape[0], F.shape[1]
+        R = T.shape[0]
+        if T.shape != (R, K) or W.shape != (K, R):
+            raise ValueError("T must be [R, K] and W [K, R]")
+        T = T.to(device=self.device, dtype=torch.float64).contiguous()
+        W = W.to(device=self.device, dtype=torch.float64).contiguous()
+        if out is None:
+            out = torch.empty_like(F)
+        need = int(lib().qcoll_dg_workspace_bytes(self._h, E, K, R))
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        _check(lib().qcoll_dg_collide(self._h, E, K, R, _ptr(T), _ptr(W), _ptr(F), _ptr(out), int(bool(conserve)),
+                                      _ptr(ws), ws.numel(), _stream(stream)))
+        return out
+
+    def set_chunk(self, items):
+        _check(lib().qcoll_plan_set_chunk(self._h, int(items)))
+        self._ws = None
+
+    def autotune(self, f, Q=None, stream=None):
+        """Time the candidate schedules on f and keep the fastest; returns (schedule, chunk)."""
+        import torch
+        batch = self._check_f(f, "f")
+        if Q is None:
+            Q = torch.empty_like(f)
+        need = int(lib().qcoll_autotune_workspace_bytes(self._h, batch))
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        sch, ck = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().qcoll_autotune(self._h, batch, _ptr(f), _ptr(Q), _ptr(ws), ws.numel(), _stream(stream),
+                                    ctypes.byref(sch), ctypes.byref(ck)))
+        self._ws = None
+        return sch.value, ck.value
+
     def poll(self):
         _check(lib().qcoll_poll(self._h))
 
@@ -262,6 +315,70 @@ def timing_read():
         _check(lib().qcoll_timing_read(name.encode(), ctypes.byref(ms), ctypes.byref(n)))
         out[name] = (ms.value, n.value)
     return out
+
+
+class Group:
+    """Several plans with their item counts evaluated as one (graph) launch."""
+
+    def __init__(self, plans, counts):
+        self.plans = list(plans)
+        self.counts = [int(c) for c in counts]
+        n = len(self.plans)
+        hp = (ctypes.c_void_p * n)(*[p._h for p in self.plans])
+        hc = (ctypes.c_int64 * n)(*self.counts)
+        h = ctypes.c_void_p()
+        _check(lib().qcoll_group_create(hp, hc, n, ctypes.byref(h)))
+        self._h = h
+        self._ws = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            import torch
+            torch.cuda.synchronize()
+            lib().qcoll_group_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _workspace(self, op):
+        import torch
+        need = int(lib().qcoll_group_workspace_bytes(self._h, op))
+        ws = self._ws.get(op)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.plans[0].device)
+            self._ws[op] = ws
+        return ws
+
+    @staticmethod
+    def _arr(ts):
+        return (ctypes.c_void_p * len(ts))(*[t.data_ptr() if t is not None else None for t in ts])
+
+    def eval(self, fs, Qs=None, conserve=True, use_graph=True, stream=None):
+        import torch
+        if Qs is None:
+            Qs = [torch.empty_like(f) for f in fs]
+        for p, f, q, c in zip(self.plans, fs, Qs, self.counts):
+            if p._check_f(f, "f") != c or p._check_f(q, "Q") != c:
+                raise ValueError("item counts differ from the group's")
+        ws = self._workspace(0)
+        _check(lib().qcoll_group_eval(self._h, self._arr(fs), self._arr(Qs), int(bool(conserve)), _ptr(ws),
+                                      ws.numel(), _stream(stream), int(bool(use_graph))))
+        return Qs
+
+    def vjp(self, fs, gs, dfs=None, domegas=None, through_conserve=True, use_graph=True, stream=None):
+        import torch
+        if dfs is None:
+            dfs = [torch.empty_like(f) for f in fs]
+        ws = self._workspace(1)
+        dw = self._arr(domegas) if domegas is not None else None
+        _check(lib().qcoll_group_vjp(self._h, self._arr(fs), self._arr(gs), self._arr(dfs), dw,
+                                     int(bool(through_conserve)), _ptr(ws), ws.numel(), _stream(stream),
+                                     int(bool(use_graph))))
+        return dfs
 
 
 def collide(f, plan, omega=None, conserve=True):

@@ -1,14 +1,11 @@
 // C ABI: argument validation, plan lifetime and dispatch.
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <string>
 
 #include "qcoll_internal.h"
-
-struct qcoll_plan_s {
-  qcoll::Plan p;
-};
 
 namespace qcoll {
 qcoll_status plan_build(Plan &p, const qcoll_params &prm);
@@ -184,6 +181,7 @@ qcoll_status qcoll_conserve(qcoll_plan plan, int64_t batch, double *Q, double *m
   if (batch < 0) return fail(QCOLL_EINVAL, "batch must be >= 0");
   if (batch == 0) return QCOLL_OK;
   if (!Q) return fail(QCOLL_EINVAL, "Q must be non-NULL");
+  if (reinterpret_cast<uintptr_t>(Q) % 16) return fail(QCOLL_EINVAL, "Q must be 16-byte aligned");
   if (batch > 0x7fffffff) return fail(QCOLL_EINVAL, "batch too large");
   qcoll_status st = check_device(plan->p);
   if (st != QCOLL_OK) return st;
@@ -220,6 +218,42 @@ qcoll_status qcoll_vjp(qcoll_plan plan, int64_t batch, const double *f, const do
   if (st != QCOLL_OK) return st;
   return qcoll::launch_vjp(plan->p, batch, f, g, df, domega, through_conserve != 0, ws, lay,
                            static_cast<hipStream_t>(stream));
+}
+
+size_t qcoll_dg_workspace_bytes(qcoll_plan plan, int64_t n_elem, int32_t K, int32_t R) {
+  if (!plan || n_elem < 0 || K < 1 || R < 1) return 0;
+  const size_t n3 = size_t(plan->p.n3());
+  const size_t terms = size_t(n_elem) * R;
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  return 2 * al(terms * n3 * sizeof(double)) + qcoll::make_layout(plan->p, int64_t(terms), 0).total;
+}
+
+qcoll_status qcoll_dg_collide(qcoll_plan plan, int64_t n_elem, int32_t K, int32_t R, const double *T,
+                              const double *W, const double *F, double *C, int32_t conserve, void *ws,
+                              size_t ws_bytes, void *stream) {
+  if (!plan) return fail(QCOLL_EINVAL, "plan is NULL");
+  if (n_elem < 0) return fail(QCOLL_EINVAL, "n_elem must be >= 0");
+  if (K < 1 || K > 64 || R < 1 || R > 4096) return fail(QCOLL_EINVAL, "need 1 <= K <= 64 and 1 <= R <= 4096");
+  if (n_elem == 0) return QCOLL_OK;
+  if (!T || !W || !F || !C) return fail(QCOLL_EINVAL, "T, W, F and C must be non-NULL");
+  const size_t n3 = size_t(plan->p.n3());
+  const size_t terms = size_t(n_elem) * R;
+  if (terms > size_t(0x7fffffff)) return fail(QCOLL_EINVAL, "n_elem * R too large");
+  const size_t need = qcoll_dg_workspace_bytes(plan, n_elem, K, R);
+  if (!ws || ws_bytes < need) return fail(QCOLL_EWORKSPACE, "workspace missing or smaller than qcoll_dg_workspace_bytes");
+  qcoll_status st = check_device(plan->p);
+  if (st != QCOLL_OK) return st;
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  char *w = static_cast<char *>(ws);
+  double *Hd = reinterpret_cast<double *>(w);
+  double *Qd = reinterpret_cast<double *>(w + al(terms * n3 * sizeof(double)));
+  void *ews = w + 2 * al(terms * n3 * sizeof(double));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = qcoll::launch_dg_contract(T, F, Hd, n_elem, R, K, long(n3), s)) != QCOLL_OK) return st;
+  const qcoll::Layout lay = qcoll::make_layout(plan->p, int64_t(terms), 0);
+  if ((st = qcoll::launch_eval(plan->p, int64_t(terms), Hd, Qd, ews, lay, s)) != QCOLL_OK) return st;
+  if (conserve && (st = qcoll::launch_conserve(plan->p, int64_t(terms), Qd, nullptr, s)) != QCOLL_OK) return st;
+  return qcoll::launch_dg_contract(W, Qd, C, n_elem, K, R, long(n3), s);
 }
 
 qcoll_status qcoll_poll(qcoll_plan plan) {

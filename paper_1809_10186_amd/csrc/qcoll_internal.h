@@ -20,6 +20,7 @@ struct Plan {
   bool truncated = false;        // SVD truncation requested (any svd_rank >= 0)
   bool mix_identity = true;      // B_s = A_s (no SVD rotation)
   int schedule = 0;              // hot-loop schedule: 0 auto, 1 two-pass, 2 fused
+  int chunk = 0;                 // items per eval chunk (0: default 64)
   double sigma_max = 0, sigma_min_kept = 0;
 
   std::vector<double> rho, w_rho;          // radial rule
@@ -66,6 +67,8 @@ qcoll_status launch_vjp(const Plan &p, int64_t batch, const double *f, const dou
                         hipStream_t st);
 
 bool supported_N(int N);
+qcoll_status launch_dg_contract(const double *A, const double *X, double *Y, long E, int rows, int cols, long n3,
+                                hipStream_t st);
 bool fused_gain_supported(int N, int precision);
 bool use_fused_gain(const Plan &p);
 qcoll_status launch_gain_fused(const Plan &p, const void *H, void *W, long nbp, hipStream_t st);
@@ -88,3 +91,7 @@ struct TimedLaunch {
 };
 
 }  // namespace qcoll
+
+struct qcoll_plan_s {
+  qcoll::Plan p;
+};

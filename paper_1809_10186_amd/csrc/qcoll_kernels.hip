@@ -116,25 +116,26 @@ struct OpLowRank {
   }
 };
 
-// fused schedule, gain inverse slab pass: sum over the radial nodes of the
-// per-node gain spectra W[b][p], slab g = item*N + k1
-template <typename T, int N>
-struct SrcSumP {
-  const C<T> *W;
-  int Nr;
-  __device__ C<T> operator()(long g, int r, int c) const {
-    constexpr long n3 = long(N) * N * N;
-    const long b = g / N;
-    const long o = ((g % N) * N + r) * N + c;
-    T re = T(0), im = T(0);
-    for (int p = 0; p < Nr; ++p) {
-      const C<T> v = W[(b * Nr + p) * n3 + o];
-      re += v.re;
-      im += v.im;
-    }
-    return C<T>{re, im};
+// fused schedule: gain spectrum = sum over the radial nodes of the per-node
+// spectra W[b][p]; two complex values per lane (16-byte loads), node loop
+// unrolled so that the loads of several nodes are in flight together
+__global__ __launch_bounds__(256) void k_sum_nodes(const float4 *__restrict__ W, float4 *__restrict__ out,
+                                                   long nitems, int Nr, long n3h) {
+  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nitems * n3h) return;
+  const long b = i / n3h, o = i % n3h;
+  const float4 *w = W + b * Nr * n3h + o;
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 8
+  for (int p = 0; p < Nr; ++p) {
+    const float4 v = w[p * n3h];
+    acc.x += v.x;
+    acc.y += v.y;
+    acc.z += v.z;
+    acc.w += v.w;
   }
-};
+  out[i] = acc;
+}
 
 // loss, slab pass (FP64): Lambda * H64, slab g = item*N + k1
 template <int N>
@@ -250,7 +251,15 @@ struct Engine {
           // gain terms and the low-rank stage on chip; W[b][p] = alpha_p fft3(A_p)
           C<T> *Wp = reinterpret_cast<C<T> *>(A);
           if ((s = launch_gain_fused(p, H, Wp, nb * p.N_rho, st))) return s;
-          if ((s = slab<SrcSumP<T, N>, DstCplx<T, N>, +1>(SrcSumP<T, N>{Wp, p.N_rho}, DstCplx<T, N>{TA}, nb * N, st,
+          {
+            // n3 is even for every supported N, so the float4 view is exact
+            TimedLaunch tl("sum nodes", st);
+            const long n3h = n3 / 2;
+            hipLaunchKernelGGL(k_sum_nodes, dim3(nblk(nb * n3h, 256)), dim3(256), 0, st,
+                               reinterpret_cast<const float4 *>(Wp), reinterpret_cast<float4 *>(TA), nb, p.N_rho, n3h);
+            QC_LAUNCH_CHECK("sum nodes");
+          }
+          if ((s = slab<SrcCplx<T, N>, DstCplx<T, N>, +1>(SrcCplx<T, N>{TA}, DstCplx<T, N>{TA}, nb * N, st,
                                                            "gain inverse slab")))
             return s;
           if ((s = Passes<double, N>::template slab<SrcLoss<N>, DstCplx<double, N>, +1>(
@@ -289,25 +298,33 @@ struct Engine {
 };
 
 // ----------------------------------------------------------------------------
-// FP64 conservation projection: one workgroup per item.
-__global__ __launch_bounds__(256) void k_conserve(double *Q, double *mom, const double *ginv, int N, double L,
-                                                  int *flag, double dc3) {
+// FP64 conservation projection: one 1024-lane workgroup per item.  Each lane
+// walks pairs of consecutive points along the last axis (16-byte loads); the
+// velocity of a point is rebuilt from its index.  The five sums are reduced
+// in a fixed order, so the result is deterministic.
+__global__ __launch_bounds__(1024) void k_conserve(double *Q, double *mom, const double *ginv, int N, double L,
+                                                   int *flag, double dc3) {
   const long n3 = long(N) * N * N;
   const long b = blockIdx.x;
-  double *q = Q + b * n3;
+  double2 *q = reinterpret_cast<double2 *>(Q + b * n3);
   const double dc = 2.0 * L / N;
+  const long nh = n3 / 2;   // N is even: a pair never crosses a row
   double s[5] = {0, 0, 0, 0, 0};
-  for (long j = threadIdx.x; j < n3; j += blockDim.x) {
+  for (long h = threadIdx.x; h < nh; h += blockDim.x) {
+    const long j = 2 * h;
     const int i1 = int(j / (N * N)), i2 = int((j / N) % N), i3 = int(j % N);
-    const double c1 = -L + (i1 + 0.5) * dc, c2 = -L + (i2 + 0.5) * dc, c3 = -L + (i3 + 0.5) * dc;
-    const double v = q[j];
-    s[0] += v;
-    s[1] += v * c1;
-    s[2] += v * c2;
-    s[3] += v * c3;
-    s[4] += v * (c1 * c1 + c2 * c2 + c3 * c3);
+    const double c1 = -L + (i1 + 0.5) * dc, c2 = -L + (i2 + 0.5) * dc;
+    const double c3a = -L + (i3 + 0.5) * dc, c3b = c3a + dc;
+    const double2 v = q[h];
+    const double sv = v.x + v.y;
+    const double r12 = c1 * c1 + c2 * c2;
+    s[0] += sv;
+    s[1] += sv * c1;
+    s[2] += sv * c2;
+    s[3] += v.x * c3a + v.y * c3b;
+    s[4] += v.x * (r12 + c3a * c3a) + v.y * (r12 + c3b * c3b);
   }
-  __shared__ double red[5][256];
+  __shared__ double red[5][1024];
   for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = s[k];
   __syncthreads();
   for (int w = blockDim.x / 2; w > 0; w >>= 1) {
@@ -329,10 +346,16 @@ __global__ __launch_bounds__(256) void k_conserve(double *Q, double *mom, const 
       for (int k = 0; k < 5; ++k) mom[b * 5 + k] = m[k] * dc3;
     if (!finite) atomicOr(flag, 1);
   }
-  for (long j = threadIdx.x; j < n3; j += blockDim.x) {
+  for (long h = threadIdx.x; h < nh; h += blockDim.x) {
+    const long j = 2 * h;
     const int i1 = int(j / (N * N)), i2 = int((j / N) % N), i3 = int(j % N);
-    const double c1 = -L + (i1 + 0.5) * dc, c2 = -L + (i2 + 0.5) * dc, c3 = -L + (i3 + 0.5) * dc;
-    q[j] -= lam[0] + lam[1] * c1 + lam[2] * c2 + lam[3] * c3 + lam[4] * (c1 * c1 + c2 * c2 + c3 * c3);
+    const double c1 = -L + (i1 + 0.5) * dc, c2 = -L + (i2 + 0.5) * dc;
+    const double c3a = -L + (i3 + 0.5) * dc, c3b = c3a + dc;
+    const double base = lam[0] + lam[1] * c1 + lam[2] * c2 + lam[4] * (c1 * c1 + c2 * c2);
+    double2 v = q[h];
+    v.x -= base + lam[3] * c3a + lam[4] * c3a * c3a;
+    v.y -= base + lam[3] * c3b + lam[4] * c3b * c3b;
+    q[h] = v;
   }
 }
 
@@ -432,7 +455,8 @@ Layout make_layout(const Plan &p, int64_t batch, int op) {
     l.total = o;
     return l;
   }
-  l.bc = batch < 64 ? (batch > 0 ? batch : 1) : 64;
+  const long cmax = p.chunk > 0 ? p.chunk : 64;
+  l.bc = batch < cmax ? (batch > 0 ? batch : 1) : cmax;
   l.pc = 128;
   if (l.pc > l.bc * p.N_rho) l.pc = l.bc * p.N_rho;
   l.off_h = o; o += al(size_t(l.bc) * n3 * 2 * es);
@@ -472,7 +496,7 @@ qcoll_status launch_eval(const Plan &p, int64_t batch, const double *f, double *
 qcoll_status launch_conserve(const Plan &p, int64_t batch, double *Q, double *mom, hipStream_t st) {
   const double dc = 2.0 * p.L / p.N;
   TimedLaunch tl("conserve", st);
-  hipLaunchKernelGGL(k_conserve, dim3(unsigned(batch)), dim3(256), 0, st, Q, mom, p.ginv, p.N, p.L, p.flag,
+  hipLaunchKernelGGL(k_conserve, dim3(unsigned(batch)), dim3(1024), 0, st, Q, mom, p.ginv, p.N, p.L, p.flag,
                      dc * dc * dc);
   QC_LAUNCH_CHECK("conserve");
   return QCOLL_OK;

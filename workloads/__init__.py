@@ -98,6 +98,23 @@ WORKLOADS = {
     "adjoint_32": dict(N=32, L=6.0, M=12, N_rho=16, omega=0.81, prefactor=None, items=256, seed=4),
 }
 
+# Uneven batch over three velocity grids (shock-like hot/cold states): 2048
+# points split 50/35/15 % (rounded half-to-even: 1024/717/307), each grid with
+# its own temperature band and maximum drift; M = 12, omega = 0.81, gain table
+# truncated by SVD at 1e-6.
+UNEVEN = [
+    dict(N=24, L=6.0, N_rho=16, items=1024, T_range=(1.0, 1.5), u_max=0.5, seed=5),
+    dict(N=32, L=7.0, N_rho=16, items=717, T_range=(1.5, 2.5), u_max=1.2, seed=6),
+    dict(N=48, L=9.0, N_rho=24, items=307, T_range=(2.5, 3.5), u_max=2.3, seed=7),
+]
+UNEVEN_COMMON = dict(M=12, omega=0.81, svd_tol=1e-6)
+
+
+def uneven_grid(i, items=None):
+    g = UNEVEN[i]
+    n = g["items"] if items is None else items
+    return maxwellian_mixture(n, g["N"], g["L"], g["seed"], T_range=g["T_range"], u_max=g["u_max"])
+
 
 def mixture_for(name, items=None):
     w = WORKLOADS[name]
