@@ -48,6 +48,9 @@ struct FusedGeom {
   static constexpr int PPL = 1;
   static constexpr int NL = N * N / PPL;
   static constexpr int S1 = N * N + 32;
+  // the B <-> C transposes stay inside a wave when a wave owns whole rows
+  // (64 lanes = 64/N rows of N lanes, one pencil per lane)
+  static constexpr bool WAVE_BC = (PPL == 1) && (64 % N == 0);
   static constexpr size_t lds_bytes = size_t(N) * S1 * sizeof(float);
 };
 
@@ -66,6 +69,30 @@ __device__ __forceinline__ void lds_transpose(float *lds, float (*v)[N], WA wa, 
     });
   });
   __syncthreads();
+}
+
+// Same transpose within one wave: every address a lane writes or reads lies in
+// rows owned by its own wave, so ordering the wave's LDS writes before its
+// reads is enough (LDS requests of one wave are served in order; the fences
+// stop the compiler from moving the accesses across each other).
+template <int N, int PPL, class WA, class RA>
+__device__ __forceinline__ void lds_transpose_wave(float *lds, float (*v)[N], WA wa, RA ra) {
+  static_for<0, PPL>([&](auto u) {
+    static_for<0, N>([&](auto i) {
+      lds[wa(decltype(u)::value, decltype(i)::value)] = v[decltype(u)::value][decltype(i)::value];
+    });
+  });
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  static_for<0, PPL>([&](auto u) {
+    static_for<0, N>([&](auto i) {
+      v[decltype(u)::value][decltype(i)::value] = lds[ra(decltype(u)::value, decltype(i)::value)];
+    });
+  });
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <int N>
@@ -108,6 +135,9 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<floa
   const __amdgpu_buffer_rsrc_t hr = make_rsrc(H + b * n3, unsigned(n3 * sizeof(cplx<float>)));
   for (int q = 0; q < M; ++q) {
     const cplx<float> *ph = phase + size_t(p * M + q) * 3 * N;
+    // the previous iteration's last reads (wave-local B -> C) must finish
+    // before this iteration's A -> B writes reach other waves' rows
+    if constexpr (G::WAVE_BC) __syncthreads();
     float zr[PPL][N], zi[PPL][N];
     // stage A: lane (k2, k3) = (hi, lo); c(k1) = Re(b1 b23) + Im(b1 b23)
     static_for<0, PPL>([&](auto uu) {
@@ -130,14 +160,36 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<floa
     // A -> B: element (j1, k2, k3) at j1*S1 + k2*N + k3
     auto wa1 = [&](int u, int i) { return i * S1 + hi[u] * N + lo[u]; };
     auto ra1 = [&](int u, int i) { return hi[u] * S1 + i * N + lo[u]; };
-    lds_transpose<N, PPL>(lds, zr, wa1, ra1);
-    lds_transpose<N, PPL>(lds, zi, wa1, ra1);
+    if constexpr (G::WAVE_BC) {
+      // A -> B crosses waves: barrier after the writes; the barrier after the
+      // imaginary-part reads is not needed (B -> C below stays in own rows)
+      lds_transpose<N, PPL>(lds, zr, wa1, ra1);
+      static_for<0, PPL>([&](auto u) {
+        static_for<0, N>([&](auto i) {
+          lds[wa1(decltype(u)::value, decltype(i)::value)] = zi[decltype(u)::value][decltype(i)::value];
+        });
+      });
+      __syncthreads();
+      static_for<0, PPL>([&](auto u) {
+        static_for<0, N>([&](auto i) {
+          zi[decltype(u)::value][decltype(i)::value] = lds[ra1(decltype(u)::value, decltype(i)::value)];
+        });
+      });
+    } else {
+      lds_transpose<N, PPL>(lds, zr, wa1, ra1);
+      lds_transpose<N, PPL>(lds, zi, wa1, ra1);
+    }
     static_for<0, PPL>([&](auto u) { fft_reg<N, +1, float>(zr[decltype(u)::value], zi[decltype(u)::value]); });
     // B -> C: element (j1, j2, k3) at j1*S1 + k3*(N+1) + j2
     auto wa2 = [&](int u, int i) { return hi[u] * S1 + lo[u] * (N + 1) + i; };
     auto ra2 = [&](int u, int i) { return hi[u] * S1 + i * (N + 1) + lo[u]; };
-    lds_transpose<N, PPL>(lds, zr, wa2, ra2);
-    lds_transpose<N, PPL>(lds, zi, wa2, ra2);
+    if constexpr (G::WAVE_BC) {
+      lds_transpose_wave<N, PPL>(lds, zr, wa2, ra2);
+      lds_transpose_wave<N, PPL>(lds, zi, wa2, ra2);
+    } else {
+      lds_transpose<N, PPL>(lds, zr, wa2, ra2);
+      lds_transpose<N, PPL>(lds, zi, wa2, ra2);
+    }
     const float w = wq[q];
     static_for<0, PPL>([&](auto uu) {
       constexpr int u = decltype(uu)::value;
@@ -153,6 +205,7 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<floa
   // their truncation, already / N^3), stored as the spectrum W[item][p].
   // lane (j1, j2): axis 3; lane (j1, k3): axis 2; lane (k2, k3): axis 1.
   {
+    if constexpr (G::WAVE_BC) __syncthreads();
     float zr[PPL][N], zi[PPL][N];
     static_for<0, PPL>([&](auto uu) {
       constexpr int u = decltype(uu)::value;

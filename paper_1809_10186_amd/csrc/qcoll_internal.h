@@ -15,6 +15,7 @@ void set_error(const std::string &msg);
 struct Plan {
   int device = 0;
   int N = 0, N_rho = 0, M = 0, rank = 0, precision = 0;
+  int nv = 0;                    // rows of V / U the kernels use (rank, or N_rho when the mix saves nothing)
   double L = 0, R = 0, omega = 0, b = 0;
   bool b_follows_omega = true;
   bool truncated = false;        // SVD truncation requested (any svd_rank >= 0)
@@ -40,7 +41,7 @@ struct Plan {
   double *dlog = nullptr;  // [N_rho] d ln(b rho_p^{4-2 omega}) / d omega
   int *flag = nullptr;     // non-finite flag
 
-  int npair() const { return (rank + 1) / 2; }
+  int npair() const { return (nv + 1) / 2; }
   long n3() const { return long(N) * N * N; }
 };
 

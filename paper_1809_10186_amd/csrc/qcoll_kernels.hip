@@ -234,7 +234,7 @@ struct Engine {
     C<T> *TA = reinterpret_cast<C<T> *>(w + lay.off_t);
     C<double> *LH = reinterpret_cast<C<double> *>(w + lay.off_l);
     C<T> *Y = reinterpret_cast<C<T> *>(w + lay.off_y);
-    const int S = p.rank, np = p.npair();
+    const int S = p.nv, np = p.npair();
     for (long b0 = 0; b0 < batch; b0 += lay.bc) {
       const long nb = (batch - b0 < lay.bc) ? (batch - b0) : lay.bc;
       const double *fb = f + b0 * n3;
@@ -464,7 +464,7 @@ Layout make_layout(const Plan &p, int64_t batch, int op) {
   if (p.precision == QCOLL_FP32) { l.off_h64 = o; o += al(size_t(l.bc) * n3 * 2 * sizeof(double)); }
   const bool fused = use_fused_gain(p);
   l.off_a = o; o += al(size_t(l.bc) * p.N_rho * n3 * es * (fused ? 2 : 1));
-  l.off_b = o; o += (p.mix_identity || fused) ? 0 : al(size_t(l.bc) * p.rank * n3 * es);
+  l.off_b = o; o += (p.mix_identity || fused) ? 0 : al(size_t(l.bc) * p.nv * n3 * es);
   l.off_w = o; o += fused ? 0 : al(size_t(l.bc) * p.npair() * n3 * 2 * es);
   l.off_t = o; o += al(size_t(l.bc) * n3 * 2 * es);
   l.off_l = o; o += al(size_t(l.bc) * n3 * 2 * sizeof(double));

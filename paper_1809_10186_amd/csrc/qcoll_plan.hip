@@ -161,12 +161,26 @@ static void kernel_tables(const Plan &p, std::vector<double> &alpha, std::vector
 // effective per-node gain weights sum_s U[s][p] V_s (already / N^3), for the
 // fused schedule, which transforms each A_p on chip and so cannot mix before
 // the transform
+static std::vector<double> effective_rows(const Plan &p, const std::vector<double> &Vs, const std::vector<double> &U,
+                                          int rows) {
+  const int m = p.N_rho;
+  const long n3 = p.n3();
+  std::vector<double> ae(size_t(m) * n3, 0.0);
+  for (int s = 0; s < rows; ++s)
+    for (int q = 0; q < m; ++q) {
+      const double u = U[size_t(s) * m + q];
+      if (u == 0.0) continue;
+      for (long k = 0; k < n3; ++k) ae[size_t(q) * n3 + k] += u * Vs[size_t(s) * n3 + k];
+    }
+  return ae;
+}
+
 static qcoll_status upload_alpha_eff(Plan &p, const std::vector<double> &Vs, const std::vector<double> &U) {
   if (!fused_gain_supported(p.N, p.precision)) return QCOLL_OK;
   const int m = p.N_rho;
   const long n3 = p.n3();
   std::vector<double> ae(size_t(m) * n3, 0.0);
-  for (int s = 0; s < p.rank; ++s)
+  for (int s = 0; s < p.nv; ++s)
     for (int q = 0; q < m; ++q) {
       const double u = U[size_t(s) * m + q];
       if (u == 0.0) continue;
@@ -184,6 +198,7 @@ static qcoll_status upload_kernel_tables(Plan &p) {
   p.truncated = false;
   p.mix_identity = true;
   p.rank = m;
+  p.nv = m;
   p.sigma_max = p.sigma_min_kept = 0.0;
   V = alpha;
   U.assign(size_t(m) * m, 0.0);
@@ -192,7 +207,7 @@ static qcoll_status upload_kernel_tables(Plan &p) {
   const double inv = 1.0 / double(n3);
   const int rows = 2 * p.npair();
   std::vector<double> Vs(size_t(rows) * n3, 0.0);
-  for (size_t i = 0; i < size_t(p.rank) * n3; ++i) Vs[i] = V[i] * inv;
+  for (size_t i = 0; i < size_t(p.nv) * n3; ++i) Vs[i] = V[i] * inv;
   std::vector<double> lams(lam);
   for (auto &x : lams) x *= inv;
   qcoll_status st;
@@ -248,15 +263,27 @@ static qcoll_status upload_truncated(Plan &p, int svd_rank, double svd_tol) {
   p.truncated = true;
   p.mix_identity = false;
   p.rank = r;
+  p.nv = r;
   p.sigma_max = nrm[ord[0]];
   p.sigma_min_kept = nrm[ord[r - 1]];
-  const int rows = 2 * p.npair();
   const double inv = 1.0 / double(n3);
-  std::vector<double> Vs(size_t(rows) * n3, 0.0), U(size_t(r) * m);
+  std::vector<double> Vs(size_t(r + 1) * n3, 0.0), U(size_t(r) * m);
   for (int s = 0; s < r; ++s) {
     for (long k = 0; k < n3; ++k) Vs[size_t(s) * n3 + k] = alpha[size_t(ord[s]) * n3 + k] * inv;
     for (int q = 0; q < m; ++q) U[size_t(s) * m + q] = J[size_t(ord[s]) * m + q];
   }
+  if ((r + 1) / 2 >= (m + 1) / 2) {
+    // mixing before the transforms would not save a packed transform: use the
+    // truncated table itself, alpha~_p = sum_s U[s][p] V_s, with U = I
+    std::vector<double> at = effective_rows(p, Vs, U, r);
+    p.nv = m;
+    p.mix_identity = true;
+    Vs.assign(size_t(m + 1) * n3, 0.0);
+    std::copy(at.begin(), at.end(), Vs.begin());
+    U.assign(size_t(m) * m, 0.0);
+    for (int i = 0; i < m; ++i) U[size_t(i) * m + i] = 1.0;
+  }
+  Vs.resize(size_t(2 * p.npair()) * n3);
   std::vector<double> lams(lam);
   for (auto &x : lams) x *= inv;
   qcoll_status st;

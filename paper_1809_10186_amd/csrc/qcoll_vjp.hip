@@ -315,7 +315,7 @@ struct Vjp {
     C<double> *Lm = reinterpret_cast<C<double> *>(w + lay.off_l);
     double *gproj = reinterpret_cast<double *>(w + lay.off_a);
     double *dwg = reinterpret_cast<double *>(w + lay.off_d);
-    const int S = p.rank, np = p.npair(), Nr = p.N_rho, M = p.M;
+    const int S = p.nv, np = p.npair(), Nr = p.N_rho, M = p.M;
     qcoll_status s;
     for (long b0 = 0; b0 < batch; b0 += lay.bc) {
       const long nb = (batch - b0 < lay.bc) ? (batch - b0) : lay.bc;
