@@ -133,7 +133,8 @@ qcoll_status qcoll_plan_set_omega(qcoll_plan plan, double omega);
  * available).  Results agree to rounding; workspace sizes depend on it. */
 qcoll_status qcoll_plan_set_schedule(qcoll_plan plan, int32_t schedule);
 
-/* Workspace needed by op 0 (qcoll_eval) or 1 (qcoll_vjp) for this batch. */
+/* Workspace needed by op 0 (qcoll_eval), 1 (qcoll_vjp) or 2 (qcoll_eval_bilinear)
+ * for this batch. */
 size_t qcoll_workspace_bytes(qcoll_plan plan, int64_t batch, int32_t op);
 
 /* Q(f,f) for every item (Appendix):
@@ -145,6 +146,15 @@ size_t qcoll_workspace_bytes(qcoll_plan plan, int64_t batch, int32_t op);
  * batch == 0 is a no-op. */
 qcoll_status qcoll_eval(qcoll_plan plan, int64_t batch, const double *f, double *Q,
                         void *ws, size_t ws_bytes, void *stream);
+
+/* Bilinear collision operator Q(f, g) (Appendix: the operator form
+ * Q(f,g) = int int B_sym [f(c') g(c'_*) - f(c) g(c_*)] evaluated with the same
+ * quadrature form of the kernel modes): per (rho_p, sigma_q) the gain takes
+ * (t1_f t2_g + t2_f t1_g) / 2, the loss is f * Lam~ g.  Q(f, f) equals
+ * qcoll_eval.  Two inverse transforms per term (two-pass schedule in both
+ * precisions).  f, g, Q: [batch][N^3]; workspace: qcoll_workspace_bytes(op 2). */
+qcoll_status qcoll_eval_bilinear(qcoll_plan plan, int64_t batch, const double *f, const double *g,
+                                 double *Q, void *ws, size_t ws_bytes, void *stream);
 
 /* FP64 conservation projection, in place:
  *   Q <- Q - C^T (C C^T)^{-1} C Q,  rows of C = 1, c1, c2, c3, |c|^2 on the grid,
@@ -239,6 +249,16 @@ qcoll_status qcoll_group_eval(qcoll_group group, const double *const *f, double 
 qcoll_status qcoll_group_vjp(qcoll_group group, const double *const *f, const double *const *g,
                              double *const *df, double *const *domega, int32_t through_conserve,
                              void *ws, size_t ws_bytes, void *stream, int32_t use_graph);
+
+/* The paper's SVD variant of the DG collision term with general factors:
+ *   C[e][m] = sum_r W[m][r] Q( sum_l T1[r][l] F[e][l], sum_l T2[r][l] F[e][l] )
+ * with the bilinear Q (f_r = U^m F, g_r = V^m F of the SVD H_m = U V).
+ * T1, T2: [R][K], W: [K][R] device FP64.  Workspace from
+ * qcoll_dg_svd_workspace_bytes. */
+size_t qcoll_dg_svd_workspace_bytes(qcoll_plan plan, int64_t n_elem, int32_t K, int32_t R);
+qcoll_status qcoll_dg_collide_svd(qcoll_plan plan, int64_t n_elem, int32_t K, int32_t R,
+                                  const double *T1, const double *T2, const double *W, const double *F,
+                                  double *C, int32_t conserve, void *ws, size_t ws_bytes, void *stream);
 
 /* Synchronise the device, then report and clear the non-finite flag. */
 qcoll_status qcoll_poll(qcoll_plan plan);

@@ -26,6 +26,16 @@ def gauss_nodes(P):
     return x, w
 
 
+def lgl_nodes(P):
+    """Legendre-Gauss-Lobatto nodes on [-1, 1]: the endpoints and the roots of P_P'."""
+    if P == 1:
+        return np.array([-1.0, 1.0])
+    c = np.zeros(P + 1)
+    c[P] = 1.0
+    inner = np.polynomial.legendre.legroots(np.polynomial.legendre.legder(c))
+    return np.concatenate([[-1.0], np.sort(inner), [1.0]])
+
+
 def lagrange(nodes, x):
     """phi_l(x) for every node l: [len(nodes), len(x)]."""
     x = np.atleast_1d(x)
@@ -37,15 +47,15 @@ def lagrange(nodes, x):
     return out
 
 
-def triple_tensor_1d(P):
-    nodes, _ = gauss_nodes(P)
+def triple_tensor_1d(P, basis="gauss"):
+    nodes = gauss_nodes(P)[0] if basis == "gauss" else lgl_nodes(P)
     xq, wq = np.polynomial.legendre.leggauss(3 * P + 2)   # exact for degree 3P
     ph = lagrange(nodes, xq)
     return np.einsum("q,mq,aq,bq->mab", wq, ph, ph, ph)
 
 
-def triple_tensor_2d(P):
-    H1 = triple_tensor_1d(P)
+def triple_tensor_2d(P, basis="gauss"):
+    H1 = triple_tensor_1d(P, basis)
     K1 = P + 1
     H = np.einsum("mab,ncd->mnacbd", H1, H1).reshape(K1 * K1, K1 * K1, K1 * K1)
     return H
@@ -81,6 +91,41 @@ def collision_term_direct(F, H, P):
             qab = Qd[a] if a == b else q_sym(F[a], F[b], P)
             C += H[:, a, b][:, None, None, None] * qab[None]
     return C
+
+
+def collision_term_direct_bilinear(F, H, P):
+    """C_m = sum_{l1, l2} H_{m l1 l2} Q(F_l1, F_l2) with the bilinear Q(f, g)."""
+    K = F.shape[0]
+    C = np.zeros_like(F)
+    for a in range(K):
+        for b in range(K):
+            C += H[:, a, b][:, None, None, None] * spectral.collide_fg(F[a], F[b], P)[None]
+    return C
+
+
+def svd_factors(H, tol=1e-13):
+    """The paper's SVD variant: H_m = sum_r U_{l1 r} V_{r l2} (singular values in V).
+    Returns T1 [R, K] (rows U[:, r]^T), T2 [R, K] (rows V[r, :]), W [K, R]."""
+    K = H.shape[0]
+    r1, r2, cols = [], [], []
+    for m in range(K):
+        U, s, Vt = np.linalg.svd(H[m])
+        for r in range(K):
+            if s[r] > tol * s[0]:
+                r1.append(U[:, r])
+                r2.append(s[r] * Vt[r])
+                c = np.zeros(K)
+                c[m] = 1.0
+                cols.append(c)
+    return np.array(r1), np.array(r2), np.array(cols).T
+
+
+def collision_term_svd(F, T1, T2, W, P):
+    """sum_r W[m][r] Q(T1_r . F, T2_r . F) with the bilinear Q."""
+    f = np.einsum("rk,kxyz->rxyz", T1, F)
+    g = np.einsum("rk,kxyz->rxyz", T2, F)
+    Qr = np.array([spectral.collide_fg(a, b, P) for a, b in zip(f, g)])
+    return np.einsum("kr,rxyz->kxyz", W, Qr)
 
 
 def collision_term_factored(F, T, W, P):

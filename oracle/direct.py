@@ -20,15 +20,17 @@ from . import dft
 from .spectral import beta
 
 
-def collide_direct(f, P):
+def collide_direct(f, P, g=None):
+    """Q(f, f), or the bilinear Q(f, g) when g is given (l indexes f, m indexes g)."""
     N = P.N
     n3 = N ** 3
     c = (dft.fft3(f) / n3).reshape(-1)
+    cg = c if g is None else (dft.fft3(g) / n3).reshape(-1)
     idx = np.indices((N, N, N)).reshape(3, -1)
     # k index of every (l, m) pair
     kk = ((idx[:, :, None] + idx[:, None, :]) % N)
     kflat = (kk[0] * N + kk[1]) * N + kk[2]
-    cc = np.outer(c, c)
+    cc = np.outer(c, cg)
     Qh = np.zeros(n3, dtype=complex)
     alpha = P.alpha.reshape(P.N_rho, -1)
     for p, rho in enumerate(P.kt.rho):

@@ -114,3 +114,26 @@ def collide(f, P, return_parts=False):
 
 def collide_batch(fb, P):
     return np.stack([collide(f, P) for f in fb])
+
+
+def collide_fg(f, g, P):
+    """Bilinear Q(f, g) of the Appendix (the operator the paper evaluates for
+    the weak form): gain sum_{l+m=k} G(l,m) f^_l g^_m with the quadrature form
+    of G, i.e. per (p, q) the product a_f a_g + b_f b_g of the cos- and
+    sin-weighted inverse transforms of f and g; loss f * ifft3(Lambda * fft3 g)."""
+    f = np.asarray(f, dtype=float)
+    g = np.asarray(g, dtype=float)
+    Xf = dft.fft3(f)
+    Xg = dft.fft3(g)
+    A = np.zeros((P.N_rho,) + f.shape, dtype=complex)
+    for p, rho in enumerate(P.kt.rho):
+        for q in range(P.M):
+            bt = beta(P.N, P.L, 0.5 * rho * P.sphere_pts[q], P.nyquist)
+            af = dft.ifft3(bt.real * Xf)
+            bf = dft.ifft3(bt.imag * Xf)
+            ag = dft.ifft3(bt.real * Xg)
+            bg = dft.ifft3(bt.imag * Xg)
+            A[p] += P.sphere_w[q] * (af * ag + bf * bg)
+    gp = gain(f, P, A=A)
+    lp = f * dft.ifft3(P.lam * Xg)
+    return (gp - lp).real

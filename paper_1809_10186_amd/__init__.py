@@ -66,6 +66,9 @@ def lib():
             "qcoll_status_str": ([i32], ctypes.c_char_p),
             "qcoll_last_error": ([], ctypes.c_char_p),
             "qcoll_version": ([], i32),
+            "qcoll_eval_bilinear": ([vp, i64, dp, dp, dp, vp, ctypes.c_size_t, vp], i32),
+            "qcoll_dg_svd_workspace_bytes": ([vp, i64, i32, i32], ctypes.c_size_t),
+            "qcoll_dg_collide_svd": ([vp, i64, i32, i32, dp, dp, dp, dp, dp, i32, vp, ctypes.c_size_t, vp], i32),
             "qcoll_dg_workspace_bytes": ([vp, i64, i32, i32], ctypes.c_size_t),
             "qcoll_dg_collide": ([vp, i64, i32, i32, dp, dp, dp, dp, i32, vp, ctypes.c_size_t, vp], i32),
             "qcoll_plan_set_chunk": ([vp, i32], i32),
@@ -224,6 +227,20 @@ class Plan:
         _check(lib().qcoll_eval(self._h, batch, _ptr(f), _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
         return out
 
+    def eval_bilinear(self, f, g, out=None, stream=None):
+        """Bilinear Q(f, g) for every item (two-pass schedule)."""
+        import torch
+        batch = self._check_f(f, "f")
+        if self._check_f(g, "g") != batch:
+            raise ValueError("f and g batches differ")
+        if out is None:
+            out = torch.empty_like(f)
+        need = self.workspace_bytes(batch, 2)
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        _check(lib().qcoll_eval_bilinear(self._h, batch, _ptr(f), _ptr(g), _ptr(out), _ptr(ws), ws.numel(),
+                                         _stream(stream)))
+        return out
+
     def conserve(self, Q, moments=None, stream=None):
         batch = self._check_f(Q, "Q")
         _check(lib().qcoll_conserve(self._h, batch, _ptr(Q), _ptr(moments), _stream(stream)))
@@ -272,6 +289,25 @@ class Plan:
         ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
         _check(lib().qcoll_dg_collide(self._h, E, K, R, _ptr(T), _ptr(W), _ptr(F), _ptr(out), int(bool(conserve)),
                                       _ptr(ws), ws.numel(), _stream(stream)))
+        return out
+
+    def dg_collide_svd(self, F, T1, T2, W, conserve=False, out=None, stream=None):
+        """The paper's SVD form: C[e][m] = sum_r W[m][r] Q(T1_r . F[e], T2_r . F[e]) (bilinear Q)."""
+        import torch
+        n = self.N
+        if F.dim() != 5 or F.shape[2:] != (n, n, n) or F.dtype != torch.float64 or not F.is_contiguous():
+            raise ValueError("F must be a contiguous float64 tensor [n_elem, K, N, N, N]")
+        E, K = F.shape[0], F.shape[1]
+        R = T1.shape[0]
+        if T1.shape != (R, K) or T2.shape != (R, K) or W.shape != (K, R):
+            raise ValueError("T1, T2 must be [R, K] and W [K, R]")
+        T1, T2, W = [x.to(device=self.device, dtype=torch.float64).contiguous() for x in (T1, T2, W)]
+        if out is None:
+            out = torch.empty_like(F)
+        need = int(lib().qcoll_dg_svd_workspace_bytes(self._h, E, K, R))
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        _check(lib().qcoll_dg_collide_svd(self._h, E, K, R, _ptr(T1), _ptr(T2), _ptr(W), _ptr(F), _ptr(out),
+                                          int(bool(conserve)), _ptr(ws), ws.numel(), _stream(stream)))
         return out
 
     def set_chunk(self, items):

@@ -156,7 +156,7 @@ qcoll_status qcoll_plan_set_schedule(qcoll_plan plan, int32_t schedule) {
 }
 
 size_t qcoll_workspace_bytes(qcoll_plan plan, int64_t batch, int32_t op) {
-  if (!plan || batch < 0 || (op != 0 && op != 1)) return 0;
+  if (!plan || batch < 0 || op < 0 || op > 2) return 0;
   return qcoll::make_layout(plan->p, batch, op).total;
 }
 
@@ -174,6 +174,24 @@ qcoll_status qcoll_eval(qcoll_plan plan, int64_t batch, const double *f, double 
   qcoll_status st = check_device(plan->p);
   if (st != QCOLL_OK) return st;
   return qcoll::launch_eval(plan->p, batch, f, Q, ws, lay, static_cast<hipStream_t>(stream));
+}
+
+qcoll_status qcoll_eval_bilinear(qcoll_plan plan, int64_t batch, const double *f, const double *g, double *Q,
+                                 void *ws, size_t ws_bytes, void *stream) {
+  if (!plan) return fail(QCOLL_EINVAL, "plan is NULL");
+  if (batch < 0) return fail(QCOLL_EINVAL, "batch must be >= 0");
+  if (batch == 0) return QCOLL_OK;
+  if (!f || !g || !Q) return fail(QCOLL_EINVAL, "f, g and Q must be non-NULL");
+  const long n3 = plan->p.n3();
+  auto overlap = [&](const void *a) {
+    return a < (const void *)(Q + batch * n3) && (const void *)Q < (const void *)((const double *)a + batch * n3);
+  };
+  if (overlap(f) || overlap(g)) return fail(QCOLL_EINVAL, "Q must not overlap f or g");
+  const qcoll::Layout lay = qcoll::make_layout(plan->p, batch, 2);
+  if (!ws || ws_bytes < lay.total) return fail(QCOLL_EWORKSPACE, "workspace missing or smaller than qcoll_workspace_bytes(op 2)");
+  qcoll_status st = check_device(plan->p);
+  if (st != QCOLL_OK) return st;
+  return qcoll::launch_eval2(plan->p, batch, f, g, Q, ws, lay, static_cast<hipStream_t>(stream));
 }
 
 qcoll_status qcoll_conserve(qcoll_plan plan, int64_t batch, double *Q, double *moments, void *stream) {
@@ -252,6 +270,45 @@ qcoll_status qcoll_dg_collide(qcoll_plan plan, int64_t n_elem, int32_t K, int32_
   if ((st = qcoll::launch_dg_contract(T, F, Hd, n_elem, R, K, long(n3), s)) != QCOLL_OK) return st;
   const qcoll::Layout lay = qcoll::make_layout(plan->p, int64_t(terms), 0);
   if ((st = qcoll::launch_eval(plan->p, int64_t(terms), Hd, Qd, ews, lay, s)) != QCOLL_OK) return st;
+  if (conserve && (st = qcoll::launch_conserve(plan->p, int64_t(terms), Qd, nullptr, s)) != QCOLL_OK) return st;
+  return qcoll::launch_dg_contract(W, Qd, C, n_elem, K, R, long(n3), s);
+}
+
+size_t qcoll_dg_svd_workspace_bytes(qcoll_plan plan, int64_t n_elem, int32_t K, int32_t R) {
+  if (!plan || n_elem < 0 || K < 1 || R < 1) return 0;
+  const size_t n3 = size_t(plan->p.n3());
+  const size_t terms = size_t(n_elem) * R;
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  return 3 * al(terms * n3 * sizeof(double)) + qcoll::make_layout(plan->p, int64_t(terms), 2).total;
+}
+
+qcoll_status qcoll_dg_collide_svd(qcoll_plan plan, int64_t n_elem, int32_t K, int32_t R, const double *T1,
+                                  const double *T2, const double *W, const double *F, double *C, int32_t conserve,
+                                  void *ws, size_t ws_bytes, void *stream) {
+  if (!plan) return fail(QCOLL_EINVAL, "plan is NULL");
+  if (n_elem < 0) return fail(QCOLL_EINVAL, "n_elem must be >= 0");
+  if (K < 1 || K > 64 || R < 1 || R > 4096) return fail(QCOLL_EINVAL, "need 1 <= K <= 64 and 1 <= R <= 4096");
+  if (n_elem == 0) return QCOLL_OK;
+  if (!T1 || !T2 || !W || !F || !C) return fail(QCOLL_EINVAL, "T1, T2, W, F and C must be non-NULL");
+  const size_t n3 = size_t(plan->p.n3());
+  const size_t terms = size_t(n_elem) * R;
+  if (terms > size_t(0x7fffffff)) return fail(QCOLL_EINVAL, "n_elem * R too large");
+  if (!ws || ws_bytes < qcoll_dg_svd_workspace_bytes(plan, n_elem, K, R))
+    return fail(QCOLL_EWORKSPACE, "workspace missing or smaller than qcoll_dg_svd_workspace_bytes");
+  qcoll_status st = check_device(plan->p);
+  if (st != QCOLL_OK) return st;
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t vol = al(terms * n3 * sizeof(double));
+  char *w = static_cast<char *>(ws);
+  double *Hf = reinterpret_cast<double *>(w);
+  double *Hg = reinterpret_cast<double *>(w + vol);
+  double *Qd = reinterpret_cast<double *>(w + 2 * vol);
+  void *ews = w + 3 * vol;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = qcoll::launch_dg_contract(T1, F, Hf, n_elem, R, K, long(n3), s)) != QCOLL_OK) return st;
+  if ((st = qcoll::launch_dg_contract(T2, F, Hg, n_elem, R, K, long(n3), s)) != QCOLL_OK) return st;
+  const qcoll::Layout lay = qcoll::make_layout(plan->p, int64_t(terms), 2);
+  if ((st = qcoll::launch_eval2(plan->p, int64_t(terms), Hf, Hg, Qd, ews, lay, s)) != QCOLL_OK) return st;
   if (conserve && (st = qcoll::launch_conserve(plan->p, int64_t(terms), Qd, nullptr, s)) != QCOLL_OK) return st;
   return qcoll::launch_dg_contract(W, Qd, C, n_elem, K, R, long(n3), s);
 }

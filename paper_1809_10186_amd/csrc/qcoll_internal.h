@@ -51,6 +51,7 @@ struct Layout {
   long pc = 0;          // eval: (item, radial node) pairs per hot-loop launch; vjp: items per sub-chunk
   size_t off_h = 0, off_h64 = 0, off_a = 0, off_b = 0, off_w = 0, off_t = 0, off_l = 0, off_y = 0;
   size_t off_g = 0, off_z = 0, off_hp = 0, off_d = 0;  // vjp extras
+  size_t off_hg = 0, off_h64g = 0, off_yg = 0;          // bilinear extras
   size_t total = 0;
 };
 
@@ -58,6 +59,8 @@ Layout make_layout(const Plan &p, int64_t batch, int op);
 
 qcoll_status launch_eval(const Plan &p, int64_t batch, const double *f, double *Q, void *ws,
                          const Layout &lay, hipStream_t st);
+qcoll_status launch_eval2(const Plan &p, int64_t batch, const double *f, const double *g, double *Q, void *ws,
+                          const Layout &lay, hipStream_t st);
 qcoll_status launch_conserve(const Plan &p, int64_t batch, double *Q, double *mom, hipStream_t st);
 qcoll_status launch_project(const Plan &p, int64_t batch, const double *in, double *out,
                             hipStream_t st);

@@ -48,6 +48,43 @@ struct OpGainAcc {
   }
 };
 
+// bilinear hot loop, pencil pass: u_f and u_g inverse along axis 1 for every
+// q; A_p += w_q Re(u_f u_g)  (= w_q (t1_f t2_g + t2_f t1_g) / 2)
+template <typename T, int N>
+struct OpGainAcc2 {
+  const C<T> *Yf, *Yg;
+  const T *wq;
+  T *A;
+  long bp0;
+  int M;
+  __device__ void operator()(long bpl, int r) const {
+    constexpr long n2 = long(N) * N, n3 = n2 * N;
+    T acc[N];
+    static_for<0, N>([&](auto j) { acc[decltype(j)::value] = T(0); });
+    for (int q = 0; q < M; ++q) {
+      const C<T> *yf = Yf + (bpl * M + q) * n3 + r;
+      const C<T> *yg = Yg + (bpl * M + q) * n3 + r;
+      T fr[N], fi[N], gr[N], gi[N];
+      static_for<0, N>([&](auto k) {
+        const C<T> a = yf[decltype(k)::value * n2], c = yg[decltype(k)::value * n2];
+        fr[decltype(k)::value] = a.re;
+        fi[decltype(k)::value] = a.im;
+        gr[decltype(k)::value] = c.re;
+        gi[decltype(k)::value] = c.im;
+      });
+      fft_reg<N, +1, T>(fr, fi);
+      fft_reg<N, +1, T>(gr, gi);
+      const T w = wq[q];
+      static_for<0, N>([&](auto j) {
+        constexpr int jj = decltype(j)::value;
+        acc[jj] += w * (fr[jj] * gr[jj] - fi[jj] * gi[jj]);
+      });
+    }
+    T *a = A + (bp0 + bpl) * n3 + r;
+    static_for<0, N>([&](auto j) { a[decltype(j)::value * n2] = acc[decltype(j)::value]; });
+  }
+};
+
 // low-rank mixing: B[b][s] = sum_p U[s][p] A[b][p]
 template <typename T>
 __global__ void k_mix(const T *A, const T *U, T *B, long nitems, int S, int Nr, long n3) {
@@ -223,9 +260,33 @@ struct Engine {
     return QCOLL_OK;
   }
 
-  static qcoll_status eval(const Plan &p, int64_t batch, const double *f, double *Q, void *ws,
+  // bilinear gain terms: both spectra through the slab pass, products in the pencil pass
+  static qcoll_status gain_terms2(const Plan &p, const C<T> *Hf, const C<T> *Hg, T *A, C<T> *Yf, C<T> *Yg, long nb,
+                                  long pc, hipStream_t st) {
+    const long nbp = nb * p.N_rho;
+    const T scale = T(1.0 / double(n3));
+    for (long bp0 = 0; bp0 < nbp; bp0 += pc) {
+      const long cnt = (nbp - bp0 < pc) ? (nbp - bp0) : pc;
+      qcoll_status s;
+      SrcShift<T, N> sf{Hf, reinterpret_cast<const C<T> *>(p.phase), bp0, p.M, p.N_rho, scale};
+      SrcShift<T, N> sg{Hg, reinterpret_cast<const C<T> *>(p.phase), bp0, p.M, p.N_rho, scale};
+      if ((s = slab<SrcShift<T, N>, DstCplx<T, N>, +1>(sf, DstCplx<T, N>{Yf}, cnt * p.M * N, st, "gain slab")))
+        return s;
+      if ((s = slab<SrcShift<T, N>, DstCplx<T, N>, +1>(sg, DstCplx<T, N>{Yg}, cnt * p.M * N, st, "gain slab")))
+        return s;
+      OpGainAcc2<T, N> op{Yf, Yg, reinterpret_cast<const T *>(p.wq), A, bp0, p.M};
+      if ((s = pencil(op, cnt * N * N, st, "gain pencil"))) return s;
+    }
+    return QCOLL_OK;
+  }
+
+  // Q(f, f), or the bilinear Q(f, g) when g is non-null (two-pass schedule)
+  static qcoll_status eval(const Plan &p, int64_t batch, const double *f, const double *g, double *Q, void *ws,
                            const Layout &lay, hipStream_t st) {
     char *w = static_cast<char *>(ws);
+    C<T> *Hg = reinterpret_cast<C<T> *>(w + lay.off_hg);
+    C<double> *H64g = reinterpret_cast<C<double> *>(w + lay.off_h64g);
+    C<T> *Yg = reinterpret_cast<C<T> *>(w + lay.off_yg);
     C<T> *H = reinterpret_cast<C<T> *>(w + lay.off_h);
     C<double> *H64 = reinterpret_cast<C<double> *>(w + lay.off_h64);
     T *A = reinterpret_cast<T *>(w + lay.off_a);
@@ -246,7 +307,17 @@ struct Engine {
         hipLaunchKernelGGL(k_cast<T>, dim3(nblk(nb * n3, 256)), dim3(256), 0, st, H64, H, nb * n3);
         QC_LAUNCH_CHECK("cast");
       }
-      if constexpr (std::is_same<T, float>::value) {
+      if (g) {
+        // bilinear Q(f, g): gain from both spectra, loss f * ifft(Lambda g^)
+        const double *gb = g + b0 * n3;
+        if ((s = Passes<double, N>::forward(gb, H64g, nb, st))) return s;
+        {
+          TimedLaunch tl("cast", st);
+          hipLaunchKernelGGL(k_cast<T>, dim3(nblk(nb * n3, 256)), dim3(256), 0, st, H64g, Hg, nb * n3);
+          QC_LAUNCH_CHECK("cast");
+        }
+        if ((s = gain_terms2(p, H, Hg, A, Y, Yg, nb, lay.pc, st))) return s;
+      } else if constexpr (std::is_same<T, float>::value) {
         if (use_fused_gain(p)) {
           // gain terms and the low-rank stage on chip; W[b][p] = alpha_p fft3(A_p)
           C<T> *Wp = reinterpret_cast<C<T> *>(A);
@@ -269,8 +340,10 @@ struct Engine {
           if ((s = pencil(OpAssemble<T, N>{TA, LH, fb, Q + b0 * n3}, nb * N * N, st, "assemble"))) return s;
           continue;
         }
+        if ((s = gain_terms(p, H, A, Y, nb, lay.pc, st))) return s;
+      } else {
+        if ((s = gain_terms(p, H, A, Y, nb, lay.pc, st))) return s;
       }
-      if ((s = gain_terms(p, H, A, Y, nb, lay.pc, st))) return s;
       const T *Bsrc = A;
       if (!p.mix_identity) {
         TimedLaunch tl("mix", st);
@@ -288,8 +361,8 @@ struct Engine {
                                                         "gain inverse slab")))
         return s;
       if ((s = Passes<double, N>::template slab<SrcLoss<N>, DstCplx<double, N>, +1>(
-               SrcLoss<N>{H64, reinterpret_cast<const double *>(p.lam)}, DstCplx<double, N>{LH}, nb * N, st,
-               "loss slab")))
+               SrcLoss<N>{g ? H64g : H64, reinterpret_cast<const double *>(p.lam)}, DstCplx<double, N>{LH}, nb * N,
+               st, "loss slab")))
         return s;
       if ((s = pencil(OpAssemble<T, N>{TA, LH, fb, Q + b0 * n3}, nb * N * N, st, "assemble"))) return s;
     }
@@ -457,40 +530,52 @@ Layout make_layout(const Plan &p, int64_t batch, int op) {
   }
   const long cmax = p.chunk > 0 ? p.chunk : 64;
   l.bc = batch < cmax ? (batch > 0 ? batch : 1) : cmax;
+  const bool bil = (op == 2);
   l.pc = 128;
   if (l.pc > l.bc * p.N_rho) l.pc = l.bc * p.N_rho;
   l.off_h = o; o += al(size_t(l.bc) * n3 * 2 * es);
   l.off_h64 = l.off_h;
   if (p.precision == QCOLL_FP32) { l.off_h64 = o; o += al(size_t(l.bc) * n3 * 2 * sizeof(double)); }
-  const bool fused = use_fused_gain(p);
+  const bool fused = use_fused_gain(p) && !bil;
   l.off_a = o; o += al(size_t(l.bc) * p.N_rho * n3 * es * (fused ? 2 : 1));
   l.off_b = o; o += (p.mix_identity || fused) ? 0 : al(size_t(l.bc) * p.nv * n3 * es);
   l.off_w = o; o += fused ? 0 : al(size_t(l.bc) * p.npair() * n3 * 2 * es);
   l.off_t = o; o += al(size_t(l.bc) * n3 * 2 * es);
   l.off_l = o; o += al(size_t(l.bc) * n3 * 2 * sizeof(double));
   l.off_y = o; o += fused ? 0 : al(size_t(l.pc) * p.M * n3 * 2 * es);
+  if (bil) {
+    l.off_hg = o; o += al(size_t(l.bc) * n3 * 2 * es);
+    l.off_h64g = o; o += al(size_t(l.bc) * n3 * 2 * sizeof(double));
+    l.off_yg = o; o += al(size_t(l.pc) * p.M * n3 * 2 * es);
+  }
   l.total = o;
   return l;
 }
 
 template <typename T>
-static qcoll_status eval_dispatch(const Plan &p, int64_t batch, const double *f, double *Q, void *ws,
+static qcoll_status eval_dispatch(const Plan &p, int64_t batch, const double *f, const double *g, double *Q, void *ws,
                                   const Layout &lay, hipStream_t st) {
   switch (p.N) {
-    case 8: return Engine<T, 8>::eval(p, batch, f, Q, ws, lay, st);
-    case 12: return Engine<T, 12>::eval(p, batch, f, Q, ws, lay, st);
-    case 16: return Engine<T, 16>::eval(p, batch, f, Q, ws, lay, st);
-    case 24: return Engine<T, 24>::eval(p, batch, f, Q, ws, lay, st);
-    case 32: return Engine<T, 32>::eval(p, batch, f, Q, ws, lay, st);
-    case 48: return Engine<T, 48>::eval(p, batch, f, Q, ws, lay, st);
+    case 8: return Engine<T, 8>::eval(p, batch, f, g, Q, ws, lay, st);
+    case 12: return Engine<T, 12>::eval(p, batch, f, g, Q, ws, lay, st);
+    case 16: return Engine<T, 16>::eval(p, batch, f, g, Q, ws, lay, st);
+    case 24: return Engine<T, 24>::eval(p, batch, f, g, Q, ws, lay, st);
+    case 32: return Engine<T, 32>::eval(p, batch, f, g, Q, ws, lay, st);
+    case 48: return Engine<T, 48>::eval(p, batch, f, g, Q, ws, lay, st);
     default: set_error("unsupported N"); return QCOLL_ENOTSUP;
   }
 }
 
 qcoll_status launch_eval(const Plan &p, int64_t batch, const double *f, double *Q, void *ws,
                          const Layout &lay, hipStream_t st) {
-  if (p.precision == QCOLL_FP32) return eval_dispatch<float>(p, batch, f, Q, ws, lay, st);
-  return eval_dispatch<double>(p, batch, f, Q, ws, lay, st);
+  if (p.precision == QCOLL_FP32) return eval_dispatch<float>(p, batch, f, nullptr, Q, ws, lay, st);
+  return eval_dispatch<double>(p, batch, f, nullptr, Q, ws, lay, st);
+}
+
+qcoll_status launch_eval2(const Plan &p, int64_t batch, const double *f, const double *g, double *Q, void *ws,
+                          const Layout &lay, hipStream_t st) {
+  if (p.precision == QCOLL_FP32) return eval_dispatch<float>(p, batch, f, g, Q, ws, lay, st);
+  return eval_dispatch<double>(p, batch, f, g, Q, ws, lay, st);
 }
 
 qcoll_status launch_conserve(const Plan &p, int64_t batch, double *Q, double *mom, hipStream_t st) {

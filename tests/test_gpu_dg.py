@@ -17,11 +17,12 @@ def gpu(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
 
 
-@pytest.mark.parametrize("dim,P", [(1, 1), (1, 2), (2, 1), (2, 2)])
-def test_dg_eigen_form_matches_double_sum(dim, P):
+@pytest.mark.parametrize("dim,P,basis", [(1, 1, "gauss"), (1, 2, "gauss"), (2, 1, "gauss"), (2, 2, "gauss"),
+                                         (1, 2, "lgl"), (2, 1, "lgl")])
+def test_dg_eigen_form_matches_double_sum(dim, P, basis):
     N, L, Nr = 8, 5.0, 4
-    print(f"case dg dim={dim} P={P}", flush=True)
-    H = dg.triple_tensor_1d(P) if dim == 1 else dg.triple_tensor_2d(P)
+    print(f"case dg dim={dim} P={P} basis={basis}", flush=True)
+    H = dg.triple_tensor_1d(P, basis) if dim == 1 else dg.triple_tensor_2d(P, basis)
     K = H.shape[0]
     T, Wm, ranks = dg.eigen_factors(H)
     E = 3

@@ -340,3 +340,57 @@ def test_dg_collocation_is_q_at_quadrature_points():
     C = dg.collision_term_direct(F, Hq, P)
     ref = np.array([w[m] * spectral.collide(F[m], P) for m in range(3)])
     assert np.abs(C - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------- bilinear Q(f, g)
+def test_bilinear_reduces_to_quadratic_and_matches_direct():
+    N, L = 8, 4.0
+    P = params(N, L, 4)
+    f = W.maxwellian_mixture(1, N, L, 31, noise=0.2)[0]
+    g = W.maxwellian_mixture(1, N, L, 32, noise=0.2)[0]
+    Qff = spectral.collide(f, P)
+    assert np.abs(spectral.collide_fg(f, f, P) - Qff).max() < 1e-14 * np.abs(Qff).max()
+    Qfg = spectral.collide_fg(f, g, P)
+    Qd = direct.collide_direct(f, P, g=g)
+    assert np.abs(Qfg - Qd).max() < 1e-13 * np.abs(Qd).max()
+    # symmetric part = polarisation of the quadratic form
+    from oracle import dg
+    Qs = 0.5 * (Qfg + spectral.collide_fg(g, f, P))
+    assert np.abs(Qs - dg.q_sym(f, g, P)).max() < 1e-13 * np.abs(Qs).max()
+    # bilinear in each argument
+    assert np.abs(spectral.collide_fg(2 * f, 3 * g, P) - 6 * Qfg).max() < 1e-13 * 6 * np.abs(Qfg).max()
+
+
+def test_dg_paper_svd_form_equals_double_sum():
+    """The paper's SVD variant sum_r Q(f_r, g_r) with f_r = U F, g_r = V F (general
+    U, V from the SVD of each H_m) reproduces sum H_{m l1 l2} Q(F_l1, F_l2)."""
+    from oracle import dg
+    N, L = 8, 4.0
+    P = params(N, L, 4)
+    H = dg.triple_tensor_1d(2)
+    F = W.maxwellian_mixture(3, N, L, 33, noise=0.2)
+    T1, T2, Wm = dg.svd_factors(H)
+    Cd = dg.collision_term_direct_bilinear(F, H, P)
+    Cs = dg.collision_term_svd(F, T1, T2, Wm, P)
+    assert np.abs(Cd - Cs).max() < 1e-13 * np.abs(Cd).max()
+    # and the symmetric H makes it equal to the quadratic double sum too
+    Cq = dg.collision_term_direct(F, H, P)
+    assert np.abs(Cd - Cq).max() < 1e-13 * np.abs(Cd).max()
+
+
+def test_dg_lgl_basis_ranks():
+    """On Lagrange bases at Gauss-Lobatto nodes the slices H_m have full rank K
+    (no saving from the SVD), on Gauss nodes rank K - 1 for P = 2: the rank
+    depends on the basis, as the paper notes."""
+    from oracle import dg
+    H = dg.triple_tensor_1d(2, "lgl")
+    assert np.allclose(H, H.transpose(0, 2, 1))
+    _, _, r_lgl = dg.eigen_factors(H)
+    _, _, r_g = dg.eigen_factors(dg.triple_tensor_1d(2, "gauss"))
+    assert r_lgl == [3, 3, 3]
+    assert r_g == [2, 2, 2]
+    # partition of unity: sum_m H_{m a b} = mass matrix int phi_a phi_b
+    x, w = np.polynomial.legendre.leggauss(8)
+    ph = dg.lagrange(dg.lgl_nodes(2), x)
+    M = np.einsum("q,aq,bq->ab", w, ph, ph)
+    assert np.allclose(H.sum(axis=0), M, atol=1e-14)
