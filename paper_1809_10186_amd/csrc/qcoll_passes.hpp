@@ -3,9 +3,9 @@
 // epilogue functors, and launch helpers.
 //
 // Every 3-D transform is split in two passes over HBM:
-//   slab pass   : one workgroup holds SPB slabs (fixed first index) in LDS and
-//                 transforms the two inner axes (rows in registers, then
-//                 columns), with coalesced loads/stores of whole slabs;
+//   slab pass   : one workgroup holds SPB slabs (fixed first index) and
+//                 transforms the two inner axes (columns in registers from
+//                 the loads, rows through LDS), with coalesced loads/stores;
 //   pencil pass : one lane holds one pencil along the outer axis (stride N^2,
 //                 coalesced across lanes) and transforms it in registers.
 #pragma once
@@ -22,66 +22,68 @@ namespace qcoll {
 template <typename T>
 using C = cplx<T>;
 
-// slabs per workgroup: keep the LDS tile (re + im, padded rows) within 64 KiB
+// slabs per workgroup of the generic slab kernel: the first count whose N
+// lanes per slab fill whole waves, else the one that leaves the fewest lanes
+// idle, with the LDS tile within 64 KiB and at most 256 lanes
 template <typename T, int N>
-constexpr int spb() {
-  constexpr int by_lds = 65536 / (2 * N * (N + 1) * int(sizeof(T)));
-  constexpr int by_threads = 256 / N;
-  constexpr int s = by_lds < by_threads ? by_lds : by_threads;
-  return s < 1 ? 1 : s;
+constexpr int slab_spb() {
+  int best = 1, best_num = 0, best_den = 1;
+  for (int s = 1; s * N <= 256 && s * 2 * N * (N + 1) * int(sizeof(T)) <= 65536; ++s) {
+    const int lanes = s * N, waves = (lanes + 63) / 64;
+    if (lanes % 64 == 0) return s;
+    if (lanes * best_den > best_num * (64 * waves)) {
+      best = s;
+      best_num = lanes;
+      best_den = 64 * waves;
+    }
+  }
+  return best;
 }
 
-// 2-D transform of the SPB slabs held in LDS: rows (last axis), then columns.
-template <typename T, int N, int SPB, int SIGN>
-__device__ __forceinline__ void lds_slab_fft(T (*sre)[N][N + 1], T (*sim)[N][N + 1]) {
-  const int tid = threadIdx.x;
-  const int s = tid / N, r = tid % N;
-  T xr[N], xi[N];
-  static_for<0, N>([&](auto c) {
-    xr[decltype(c)::value] = sre[s][r][decltype(c)::value];
-    xi[decltype(c)::value] = sim[s][r][decltype(c)::value];
-  });
-  fft_reg<N, SIGN, T>(xr, xi);
-  static_for<0, N>([&](auto c) {
-    sre[s][r][decltype(c)::value] = xr[decltype(c)::value];
-    sim[s][r][decltype(c)::value] = xi[decltype(c)::value];
-  });
-  __syncthreads();
-  static_for<0, N>([&](auto rr) {
-    xr[decltype(rr)::value] = sre[s][decltype(rr)::value][r];
-    xi[decltype(rr)::value] = sim[s][decltype(rr)::value][r];
-  });
-  fft_reg<N, SIGN, T>(xr, xi);
-  static_for<0, N>([&](auto rr) {
-    sre[s][decltype(rr)::value][r] = xr[decltype(rr)::value];
-    sim[s][decltype(rr)::value][r] = xi[decltype(rr)::value];
-  });
-  __syncthreads();
-}
-
-// ----------------------------------------------------------------------------
 // Generic slab kernel: Src(g, r, c) -> C<T> loads element (r, c) of slab g with
 // any prologue; Dst(g, r, c, v) stores.  Slabs g >= nslab are skipped.
-template <typename T, int N, int SIGN, class Src, class Dst>
+//
+// Lane (s, c) owns column c of local slab s: it loads the column (consecutive
+// lanes read consecutive c, so every load is coalesced), transforms it along
+// r in registers, and passes it through LDS once for the row transforms; the
+// result goes back through LDS so that the stores are column-wise again.  The
+// slab index is fixed per lane, so whatever Src and Dst derive from it is
+// computed once.  Lanes of a slab past the end read slab nslab - 1 (always
+// valid) and store nothing.
+template <typename T, int N, int SIGN, class Src, class Dst, int SPB = slab_spb<T, N>()>
 __global__ __launch_bounds__(256) void k_slab(Src src, Dst dst, long nslab) {
-  constexpr int SPB = spb<T, N>();
   __shared__ T sre[SPB][N][N + 1];
   __shared__ T sim[SPB][N][N + 1];
-  const long g0 = long(blockIdx.x) * SPB;
-  for (int e = threadIdx.x; e < SPB * N * N; e += SPB * N) {
-    const int s = e / (N * N), rc = e % (N * N), r = rc / N, c = rc % N;
-    const long g = g0 + s;
-    C<T> v{T(0), T(0)};
-    if (g < nslab) v = src(g, r, c);
-    sre[s][r][c] = v.re;
-    sim[s][r][c] = v.im;
-  }
+  const int s = int(threadIdx.x) / N, c = int(threadIdx.x) % N;
+  const long g = long(blockIdx.x) * SPB + s;
+  const long gl = g < nslab ? g : nslab - 1;
+  T xr[N], xi[N];
+  static_for<0, N>([&](auto r) {
+    const C<T> v = src(gl, decltype(r)::value, c);
+    xr[decltype(r)::value] = v.re;
+    xi[decltype(r)::value] = v.im;
+  });
+  fft_reg<N, SIGN, T>(xr, xi);
+  static_for<0, N>([&](auto r) {
+    sre[s][decltype(r)::value][c] = xr[decltype(r)::value];
+    sim[s][decltype(r)::value][c] = xi[decltype(r)::value];
+  });
   __syncthreads();
-  lds_slab_fft<T, N, SPB, SIGN>(sre, sim);
-  for (int e = threadIdx.x; e < SPB * N * N; e += SPB * N) {
-    const int s = e / (N * N), rc = e % (N * N), r = rc / N, c = rc % N;
-    const long g = g0 + s;
-    if (g < nslab) dst(g, r, c, C<T>{sre[s][r][c], sim[s][r][c]});
+  const int row = c;
+  static_for<0, N>([&](auto k) {
+    xr[decltype(k)::value] = sre[s][row][decltype(k)::value];
+    xi[decltype(k)::value] = sim[s][row][decltype(k)::value];
+  });
+  fft_reg<N, SIGN, T>(xr, xi);
+  static_for<0, N>([&](auto k) {
+    sre[s][row][decltype(k)::value] = xr[decltype(k)::value];
+    sim[s][row][decltype(k)::value] = xi[decltype(k)::value];
+  });
+  __syncthreads();
+  if (g < nslab) {
+    static_for<0, N>([&](auto r) {
+      dst(g, decltype(r)::value, c, C<T>{sre[s][decltype(r)::value][c], sim[s][decltype(r)::value][c]});
+    });
   }
 }
 
@@ -183,13 +185,13 @@ inline unsigned nblk(long n, int b) { return unsigned((n + b - 1) / b); }
 
 template <typename T, int N>
 struct Passes {
-  static constexpr int SPB = spb<T, N>();
   static constexpr long n3 = long(N) * N * N;
 
   template <class Src, class Dst, int SIGN>
   static qcoll_status slab(Src s, Dst d, long nslab, hipStream_t st, const char *what) {
     if (nslab <= 0) return QCOLL_OK;
     TimedLaunch tl(what, st);
+    constexpr int SPB = slab_spb<T, N>();
     hipLaunchKernelGGL((k_slab<T, N, SIGN, Src, Dst>), dim3(nblk(nslab, SPB)), dim3(SPB * N), 0, st, s, d, nslab);
     QC_LAUNCH_CHECK(what);
     return QCOLL_OK;

@@ -113,58 +113,68 @@ struct OpAdjPencil {
 
 // adjoint accumulation: Z[b] slab k1 = sum_{p,q} c_s(k) * fft2d(Y_(b,p,q) slab k1)
 // over the items [ib0, ib0 + ni) of the sub-chunk; one workgroup owns SPB slabs
-// of Z (possibly of two items) and loops over all N_rho*M tasks of each.
+// of Z (possibly of two items) and loops over all N_rho*M tasks of each.  Lane
+// (s, c) owns column c of slab s, as in the generic slab kernel: the column
+// transform runs in registers straight from the coalesced loads, the row
+// transform through LDS, and the accumulators hold the lane's column.
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_adj_acc(const C<T> *Y, const C<T> *phase, C<T> *Z, long ib0, long ni,
                                                  int M, int Nr) {
-  constexpr int SPB = spb<T, N>();
+  constexpr int SPB = slab_spb<T, N>();
   constexpr long n2 = long(N) * N, n3 = n2 * N;
   __shared__ T sre[SPB][N][N + 1];
   __shared__ T sim[SPB][N][N + 1];
-  const long z0 = long(blockIdx.x) * SPB;   // first Z slab (relative to ib0)
+  const int s = int(threadIdx.x) / N, c = int(threadIdx.x) % N;
   const long nz = ni * N;
+  const long z = long(blockIdx.x) * SPB + s;   // Z slab (relative to ib0)
+  const long zl = z < nz ? z : nz - 1;
+  const long bl = zl / N;
+  const int k1 = int(zl % N);
   T ar[N], ai[N];
   static_for<0, N>([&](auto k) { ar[decltype(k)::value] = T(0); ai[decltype(k)::value] = T(0); });
   const int ntask = Nr * M;
   for (int task = 0; task < ntask; ++task) {
     const int p = task / M, q = task % M;
-    for (int e = threadIdx.x; e < SPB * N * N; e += SPB * N) {
-      const int s = e / (N * N), rc = e % (N * N), r = rc / N, c = rc % N;
-      const long z = z0 + s;
-      C<T> v{T(0), T(0)};
-      if (z < nz) {
-        const long bl = z / N;
-        const int k1 = int(z % N);
-        v = Y[((bl * Nr + p) * M + q) * n3 + (long(k1) * N + r) * N + c];
-      }
-      sre[s][r][c] = v.re;
-      sim[s][r][c] = v.im;
-    }
+    const C<T> *y = Y + ((bl * Nr + p) * M + q) * n3 + long(k1) * n2 + c;
+    T xr[N], xi[N];
+    static_for<0, N>([&](auto r) {
+      const C<T> v = y[decltype(r)::value * N];
+      xr[decltype(r)::value] = v.re;
+      xi[decltype(r)::value] = v.im;
+    });
+    fft_reg<N, -1, T>(xr, xi);
+    static_for<0, N>([&](auto r) {
+      sre[s][decltype(r)::value][c] = xr[decltype(r)::value];
+      sim[s][decltype(r)::value][c] = xi[decltype(r)::value];
+    });
     __syncthreads();
-    lds_slab_fft<T, N, SPB, -1>(sre, sim);
+    const int row = c;
+    static_for<0, N>([&](auto k) {
+      xr[decltype(k)::value] = sre[s][row][decltype(k)::value];
+      xi[decltype(k)::value] = sim[s][row][decltype(k)::value];
+    });
+    fft_reg<N, -1, T>(xr, xi);
+    static_for<0, N>([&](auto k) {
+      sre[s][row][decltype(k)::value] = xr[decltype(k)::value];
+      sim[s][row][decltype(k)::value] = xi[decltype(k)::value];
+    });
+    __syncthreads();
     const C<T> *ph = phase + size_t(p * M + q) * 3 * N;
-    static_for<0, N>([&](auto kk) {
-      const int e = threadIdx.x + decltype(kk)::value * (SPB * N);
-      const int s = e / (N * N), rc = e % (N * N), r = rc / N, c = rc % N;
-      const int k1 = int((z0 + s) % N);
-      const C<T> b1 = ph[k1], b2 = ph[N + r], b3 = ph[2 * N + c];
-      const T x12 = b1.re * b2.re - b1.im * b2.im, y12 = b1.re * b2.im + b1.im * b2.re;
-      const T cm = (x12 * b3.re - y12 * b3.im) + (x12 * b3.im + y12 * b3.re);
-      ar[decltype(kk)::value] += cm * sre[s][r][c];
-      ai[decltype(kk)::value] += cm * sim[s][r][c];
+    const C<T> b1 = ph[k1], b3 = ph[2 * N + c];
+    const T x13 = b1.re * b3.re - b1.im * b3.im, y13 = b1.re * b3.im + b1.im * b3.re;
+    static_for<0, N>([&](auto r) {
+      constexpr int rr = decltype(r)::value;
+      const C<T> b2 = ph[N + rr];
+      const T cm = (x13 * b2.re - y13 * b2.im) + (x13 * b2.im + y13 * b2.re);
+      ar[rr] += cm * sre[s][rr][c];
+      ai[rr] += cm * sim[s][rr][c];
     });
     __syncthreads();
   }
-  static_for<0, N>([&](auto kk) {
-    const int e = threadIdx.x + decltype(kk)::value * (SPB * N);
-    const int s = e / (N * N), rc = e % (N * N), r = rc / N, c = rc % N;
-    const long z = z0 + s;
-    if (z < nz) {
-      const long bl = z / N;
-      const int k1 = int(z % N);
-      Z[(ib0 + bl) * n3 + (long(k1) * N + r) * N + c] = C<T>{ar[decltype(kk)::value], ai[decltype(kk)::value]};
-    }
-  });
+  if (z < nz) {
+    C<T> *zo = Z + (ib0 + bl) * n3 + long(k1) * n2 + c;
+    static_for<0, N>([&](auto r) { zo[decltype(r)::value * N] = C<T>{ar[decltype(r)::value], ai[decltype(r)::value]}; });
+  }
 }
 
 // loss adjoint spectrum, FP64: Lam (H + i FG), slab = item*N + k1
@@ -298,7 +308,7 @@ struct Vjp {
   using P = Passes<T, N>;
   using P64 = Passes<double, N>;
   static constexpr long n3 = P::n3;
-  static constexpr int SPB = spb<T, N>();
+  static constexpr int SPB = slab_spb<T, N>();
 
   static qcoll_status run(const Plan &p, int64_t batch, const double *f, const double *g_in, double *df,
                           double *domega, bool through, void *ws, const Layout &lay, hipStream_t st) {
