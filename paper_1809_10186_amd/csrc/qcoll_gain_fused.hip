@@ -16,7 +16,8 @@
 //   stage C  lane (j1, j2): pencil along axis 3 after a second transpose;
 //            the lane owns A_p[j1][j2][:] in registers across all q.
 // The forward transform of A_p runs the same stages backwards and stores
-// W_p[k1][k2][k3] from lane (k2, k3), coalesced.
+// W_p[k1][k2][k3] for k1 <= N/2 from lane (k2, k3), coalesced (the other
+// planes follow by Hermitian symmetry).
 // Each transpose moves the real parts, then the imaginary parts, through one
 // LDS tile of N * (N^2 + 32) floats (135 KiB at N = 32).  The padding makes
 // both the writes and the reads of each transpose free of bank conflicts at
@@ -224,12 +225,14 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<floa
     static_for<0, PPL>([&](auto u) { fft_reg<N, -1, float>(zr[decltype(u)::value], zi[decltype(u)::value]); });
     lds_transpose<N, PPL>(lds, zr, ra1, wa1);
     lds_transpose<N, PPL>(lds, zi, ra1, wa1);
+    // W_p is Hermitian (A_p is real, alpha is even in k): only the planes
+    // k1 <= N/2 are stored, compactly, (N/2 + 1) N^2 values per pair
     const float *ae = alpha_eff + long(p) * n3;
-    cplx<float> *wout = W + bp * n3;
+    cplx<float> *wout = W + bp * (long(N / 2 + 1) * n2);
     static_for<0, PPL>([&](auto uu) {
       constexpr int u = decltype(uu)::value;
       fft_reg<N, -1, float>(zr[u], zi[u]);
-      static_for<0, N>([&](auto k) {
+      static_for<0, N / 2 + 1>([&](auto k) {
         constexpr int kk = decltype(k)::value;
         const long o = kk * n2 + lane + u * NL;
         const float a = ae[o];

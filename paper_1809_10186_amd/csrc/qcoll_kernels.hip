@@ -154,25 +154,48 @@ struct OpLowRank {
 };
 
 // fused schedule: gain spectrum = sum over the radial nodes of the per-node
-// spectra W[b][p]; two complex values per lane (16-byte loads), node loop
+// half spectra W[b][p] (n_in float4 each) into the item's spectrum (n_out
+// float4 apart); two complex values per lane (16-byte loads), node loop
 // unrolled so that the loads of several nodes are in flight together
 __global__ __launch_bounds__(256) void k_sum_nodes(const float4 *__restrict__ W, float4 *__restrict__ out,
-                                                   long nitems, int Nr, long n3h) {
+                                                   long nitems, int Nr, long n_in, long n_out) {
   const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= nitems * n3h) return;
-  const long b = i / n3h, o = i % n3h;
-  const float4 *w = W + b * Nr * n3h + o;
+  if (i >= nitems * n_in) return;
+  const long b = i / n_in, o = i % n_in;
+  const float4 *w = W + b * Nr * n_in + o;
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll 8
   for (int p = 0; p < Nr; ++p) {
-    const float4 v = w[p * n3h];
+    const float4 v = w[p * n_in];
     acc.x += v.x;
     acc.y += v.y;
     acc.z += v.z;
     acc.w += v.w;
   }
-  out[i] = acc;
+  out[b * n_out + o] = acc;
 }
+
+// Half spectra.  The gain and loss spectra are Hermitian (their inverse
+// transforms are real), so the fused schedule keeps only the planes
+// k1 <= N/2 of each item.  Slab g of such a pass is plane g % (N/2 + 1) of
+// item g / (N/2 + 1); its place in the full [item][k1] numbering:
+template <int N>
+__device__ __forceinline__ long half_slab(long g) {
+  constexpr int H1 = N / 2 + 1;
+  return (g / H1) * N + g % H1;
+}
+
+template <typename T, int N>
+struct SrcCplxHalf {
+  const C<T> *in;
+  __device__ C<T> operator()(long g, int r, int c) const { return in[(half_slab<N>(g) * N + r) * N + c]; }
+};
+
+template <typename T, int N>
+struct DstCplxHalf {
+  C<T> *out;
+  __device__ void operator()(long g, int r, int c, C<T> v) const { out[(half_slab<N>(g) * N + r) * N + c] = v; }
+};
 
 // loss, slab pass (FP64): Lambda * H64, slab g = item*N + k1
 template <int N>
@@ -182,6 +205,20 @@ struct SrcLoss {
   __device__ C<double> operator()(long g, int r, int c) const {
     const long o = (g * N + r) * N + c;
     const double l = lam[((g % N) * N + r) * N + c];
+    const C<double> h = H[o];
+    return C<double>{h.re * l, h.im * l};
+  }
+};
+
+// loss, slab pass over the half spectrum (FP64)
+template <int N>
+struct SrcLossHalf {
+  const C<double> *H;
+  const double *lam;
+  __device__ C<double> operator()(long g, int r, int c) const {
+    const long gf = half_slab<N>(g);
+    const long o = (gf * N + r) * N + c;
+    const double l = lam[((gf % N) * N + r) * N + c];
     const C<double> h = H[o];
     return C<double>{h.re * l, h.im * l};
   }
@@ -216,6 +253,58 @@ struct OpAssemble {
         const C<double> l = x1[decltype(k)::value * n2];
         lr[decltype(k)::value] = l.re;
         li[decltype(k)::value] = l.im;
+      });
+      fft_reg<N, +1, double>(lr, li);
+      const double *fb = f + b * n3 + r;
+      static_for<0, N>([&](auto j) {
+        constexpr int jj = decltype(j)::value;
+        out[jj] -= fb[jj * n2] * lr[jj];
+      });
+    }
+    double *qb = Q + b * n3 + r;
+    static_for<0, N>([&](auto j) { qb[decltype(j)::value * n2] = out[decltype(j)::value]; });
+  }
+};
+
+// the same assembly from half spectra: after the slab passes, plane N - k1
+// of a Hermitian spectrum is the complex conjugate of plane k1 at the same
+// (j2, j3), so each pencil is completed in registers before its transform
+template <typename T, int N>
+struct OpAssembleHalf {
+  const C<T> *TA;
+  const C<double> *LH;
+  const double *f;
+  double *Q;
+  __device__ void operator()(long b, int r) const {
+    constexpr long n2 = long(N) * N, n3 = n2 * N;
+    constexpr int H1 = N / 2 + 1;
+    double out[N];
+    {
+      T ar[N], ai[N];
+      const C<T> *x0 = TA + b * n3 + r;
+      static_for<0, H1>([&](auto k) {
+        const C<T> a = x0[decltype(k)::value * n2];
+        ar[decltype(k)::value] = a.re;
+        ai[decltype(k)::value] = a.im;
+      });
+      static_for<H1, N>([&](auto k) {
+        ar[decltype(k)::value] = ar[N - decltype(k)::value];
+        ai[decltype(k)::value] = -ai[N - decltype(k)::value];
+      });
+      fft_reg<N, +1, T>(ar, ai);
+      static_for<0, N>([&](auto j) { out[decltype(j)::value] = double(ar[decltype(j)::value]); });
+    }
+    {
+      double lr[N], li[N];
+      const C<double> *x1 = LH + b * n3 + r;
+      static_for<0, H1>([&](auto k) {
+        const C<double> l = x1[decltype(k)::value * n2];
+        lr[decltype(k)::value] = l.re;
+        li[decltype(k)::value] = l.im;
+      });
+      static_for<H1, N>([&](auto k) {
+        lr[decltype(k)::value] = lr[N - decltype(k)::value];
+        li[decltype(k)::value] = -li[N - decltype(k)::value];
       });
       fft_reg<N, +1, double>(lr, li);
       const double *fb = f + b * n3 + r;
@@ -322,22 +411,25 @@ struct Engine {
           // gain terms and the low-rank stage on chip; W[b][p] = alpha_p fft3(A_p)
           C<T> *Wp = reinterpret_cast<C<T> *>(A);
           if ((s = launch_gain_fused(p, H, Wp, nb * p.N_rho, st))) return s;
+          // half spectra from here on: planes k1 <= N/2 of every item
+          constexpr long nh = long(N / 2 + 1) * N * N;
+          constexpr int H1 = N / 2 + 1;
           {
-            // n3 is even for every supported N, so the float4 view is exact
+            // nh and n3 are even for every supported N, so the float4 view is exact
             TimedLaunch tl("sum nodes", st);
-            const long n3h = n3 / 2;
-            hipLaunchKernelGGL(k_sum_nodes, dim3(nblk(nb * n3h, 256)), dim3(256), 0, st,
-                               reinterpret_cast<const float4 *>(Wp), reinterpret_cast<float4 *>(TA), nb, p.N_rho, n3h);
+            hipLaunchKernelGGL(k_sum_nodes, dim3(nblk(nb * (nh / 2), 256)), dim3(256), 0, st,
+                               reinterpret_cast<const float4 *>(Wp), reinterpret_cast<float4 *>(TA), nb, p.N_rho,
+                               nh / 2, n3 / 2);
             QC_LAUNCH_CHECK("sum nodes");
           }
-          if ((s = slab<SrcCplx<T, N>, DstCplx<T, N>, +1>(SrcCplx<T, N>{TA}, DstCplx<T, N>{TA}, nb * N, st,
-                                                           "gain inverse slab")))
+          if ((s = slab<SrcCplxHalf<T, N>, DstCplxHalf<T, N>, +1>(SrcCplxHalf<T, N>{TA}, DstCplxHalf<T, N>{TA},
+                                                                   nb * H1, st, "gain inverse slab")))
             return s;
-          if ((s = Passes<double, N>::template slab<SrcLoss<N>, DstCplx<double, N>, +1>(
-                   SrcLoss<N>{H64, reinterpret_cast<const double *>(p.lam)}, DstCplx<double, N>{LH}, nb * N, st,
-                   "loss slab")))
+          if ((s = Passes<double, N>::template slab<SrcLossHalf<N>, DstCplxHalf<double, N>, +1>(
+                   SrcLossHalf<N>{H64, reinterpret_cast<const double *>(p.lam)}, DstCplxHalf<double, N>{LH}, nb * H1,
+                   st, "loss slab")))
             return s;
-          if ((s = pencil(OpAssemble<T, N>{TA, LH, fb, Q + b0 * n3}, nb * N * N, st, "assemble"))) return s;
+          if ((s = pencil(OpAssembleHalf<T, N>{TA, LH, fb, Q + b0 * n3}, nb * N * N, st, "assemble"))) return s;
           continue;
         }
         if ((s = gain_terms(p, H, A, Y, nb, lay.pc, st))) return s;
@@ -537,7 +629,9 @@ Layout make_layout(const Plan &p, int64_t batch, int op) {
   l.off_h64 = l.off_h;
   if (p.precision == QCOLL_FP32) { l.off_h64 = o; o += al(size_t(l.bc) * n3 * 2 * sizeof(double)); }
   const bool fused = use_fused_gain(p) && !bil;
-  l.off_a = o; o += al(size_t(l.bc) * p.N_rho * n3 * es * (fused ? 2 : 1));
+  // fused: W, the complex half spectra ((N/2 + 1) N^2 values) of every (item, node)
+  const size_t per_node = fused ? size_t(p.N / 2 + 1) * p.N * p.N * 2 : size_t(n3);
+  l.off_a = o; o += al(size_t(l.bc) * p.N_rho * per_node * es);
   l.off_b = o; o += (p.mix_identity || fused) ? 0 : al(size_t(l.bc) * p.nv * n3 * es);
   l.off_w = o; o += fused ? 0 : al(size_t(l.bc) * p.npair() * n3 * 2 * es);
   l.off_t = o; o += al(size_t(l.bc) * n3 * 2 * es);
