@@ -189,8 +189,13 @@ qcoll_status qcoll_vjp(qcoll_plan plan, int64_t batch, const double *f, const do
  * qcoll_timing_read synchronises the recorded events and returns the summed
  * duration (ms) and launch count for one name (0 and 0 if never launched);
  * qcoll_timing_names writes a '\n'-separated list of the names seen into a
- * HOST buffer of cap bytes (truncated, NUL-terminated). */
+ * HOST buffer of cap bytes (truncated, NUL-terminated).
+ * qcoll_timing_select restricts the events to one role (a HOST string,
+ * copied; NULL or "" = every role), so that a timed region can carry the
+ * events of its dominant kernel only.  qcoll_timing_reset keeps the event
+ * objects for reuse, so launches after the first round create none. */
 qcoll_status qcoll_timing_enable(int32_t on);
+qcoll_status qcoll_timing_select(const char *host_name);
 qcoll_status qcoll_timing_reset(void);
 qcoll_status qcoll_timing_read(const char *name, double *host_ms, int64_t *host_count);
 qcoll_status qcoll_timing_names(char *host_buf, size_t cap);
@@ -216,8 +221,9 @@ qcoll_status qcoll_dg_collide(qcoll_plan plan, int64_t n_elem, int32_t K, int32_
 qcoll_status qcoll_plan_set_chunk(qcoll_plan plan, int32_t items);
 
 /* Autotuner: times the candidate schedules of this plan (fused / two-pass hot
- * loop x 32, 64, 128, 256 items per chunk) with qcoll_eval on the caller's f
- * and Q (Q is overwritten), keeps the fastest in the plan and returns it in
+ * loop x 32, 64, 96, 128, 192, 256 items per chunk, each balanced over the
+ * batch as ceil(batch / ceil(batch / c)); best of two timed runs each) with qcoll_eval on the caller's f and Q (Q is overwritten), keeps the
+ * fastest in the plan and returns it in
  * *host_schedule, *host_chunk (either may be NULL).  Synchronous.  If the
  * environment variable QCOLL_AUTOTUNE_CACHE names a file, choices are read
  * from and appended to it, keyed by (arch, N, N_rho, M, precision, rank,

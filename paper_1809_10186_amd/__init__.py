@@ -84,6 +84,7 @@ def lib():
                                 ctypes.POINTER(vp), i32, vp, ctypes.c_size_t, vp, i32], i32),
             "qcoll_timing_enable": ([i32], i32),
             "qcoll_timing_reset": ([], i32),
+            "qcoll_timing_select": ([ctypes.c_char_p], i32),
             "qcoll_timing_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_int64)], i32),
             "qcoll_timing_names": ([ctypes.c_char_p, ctypes.c_size_t], i32),
@@ -335,6 +336,11 @@ class Plan:
 
 def timing_enable(on=True):
     _check(lib().qcoll_timing_enable(int(bool(on))))
+
+
+def timing_select(name=None):
+    """Time only the kernel role `name` (None: every role)."""
+    _check(lib().qcoll_timing_select(name.encode() if name else None))
 
 
 def timing_reset():

@@ -140,13 +140,16 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<floa
     // before this iteration's A -> B writes reach other waves' rows
     if constexpr (G::WAVE_BC) __syncthreads();
     float zr[PPL][N], zi[PPL][N];
-    // stage A: lane (k2, k3) = (hi, lo); c(k1) = Re(b1 b23) + Im(b1 b23)
+    // stage A: lane (k2, k3) = (hi, lo); c(k1) = Re(b1 b23) + Im(b1 b23),
+    // scaled by sqrt(w_q) (the weights are positive), so that the product
+    // below accumulates w_q (Re(u)^2 - Im(u)^2) with two FMAs per point
+    const float sc = scale * __builtin_sqrtf(wq[q]);
     static_for<0, PPL>([&](auto uu) {
       constexpr int u = decltype(uu)::value;
       const cplx<float> b2 = ph[N + hi[u]], b3 = ph[2 * N + lo[u]];
       const float xr = b2.re * b3.re - b2.im * b3.im;
       const float yi = b2.re * b3.im + b2.im * b3.re;
-      const float P = (xr + yi) * scale, Qm = (xr - yi) * scale;
+      const float P = (xr + yi) * sc, Qm = (xr - yi) * sc;
       static_for<0, N>([&](auto k) {
         constexpr int kk = decltype(k)::value;
         const cplx<float> v = load_c32(hr, int((lane + u * NL) * sizeof(cplx<float>)),
@@ -191,13 +194,13 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<floa
       lds_transpose<N, PPL>(lds, zr, wa2, ra2);
       lds_transpose<N, PPL>(lds, zi, wa2, ra2);
     }
-    const float w = wq[q];
     static_for<0, PPL>([&](auto uu) {
       constexpr int u = decltype(uu)::value;
       fft_reg<N, +1, float>(zr[u], zi[u]);
       static_for<0, N>([&](auto j) {
         constexpr int jj = decltype(j)::value;
-        acc[u][jj] += w * (zr[u][jj] * zr[u][jj] - zi[u][jj] * zi[u][jj]);
+        acc[u][jj] += zr[u][jj] * zr[u][jj];
+        acc[u][jj] -= zi[u][jj] * zi[u][jj];
       });
     });
   }

@@ -247,12 +247,25 @@ qcoll_status qcoll_plan_set_chunk(qcoll_plan plan, int32_t items) {
   return QCOLL_OK;
 }
 
+// candidate items per chunk of the autotuner: each nominal size c is
+// balanced over the batch, ceil(batch / ceil(batch / c)), so that all
+// launches of one eval have the same size; duplicates are dropped
+static std::vector<int> tune_chunks(int64_t batch) {
+  std::vector<int> out;
+  for (int c : {32, 64, 96, 128, 192, 256}) {
+    const int64_t n = (batch + c - 1) / c;
+    const int ck = int((batch + n - 1) / n);
+    if (std::find(out.begin(), out.end(), ck) == out.end()) out.push_back(ck);
+  }
+  return out;
+}
+
 size_t qcoll_autotune_workspace_bytes(qcoll_plan plan, int64_t batch) {
   if (!plan || batch <= 0) return 0;
   qcoll::Plan p = plan->p;  // copy: only schedule/chunk are varied
   size_t mx = 0;
   for (int sch : {1, 2})
-    for (int ck : {32, 64, 128, 256}) {
+    for (int ck : tune_chunks(batch)) {
       if (sch == 2 && !qcoll::fused_gain_supported(p.N, p.precision)) continue;
       p.schedule = sch;
       p.chunk = ck;
@@ -305,19 +318,24 @@ qcoll_status qcoll_autotune(qcoll_plan plan, int64_t batch, const double *f, dou
   qcoll_timing_enable(0);
   qcoll_status rc = QCOLL_OK;
   for (int sch : {2, 1})
-    for (int ck : {32, 64, 128, 256}) {
+    for (int ck : tune_chunks(batch)) {
       if (sch == 2 && !qcoll::fused_gain_supported(p.N, p.precision)) continue;
-      if (ck > 2 * batch && ck != 32) continue;
       p.schedule = sch;
       p.chunk = ck;
       const qcoll::Layout lay = qcoll::make_layout(p, batch, 0);
       if ((rc = qcoll::launch_eval(p, batch, f, Q, ws, lay, st)) != QCOLL_OK) break;  // warm-up
-      hipEventRecord(e0, st);
-      if ((rc = qcoll::launch_eval(p, batch, f, Q, ws, lay, st)) != QCOLL_OK) break;
-      hipEventRecord(e1, st);
-      hipEventSynchronize(e1);
-      float ms = 0.f;
-      hipEventElapsedTime(&ms, e0, e1);
+      // best of two timed runs
+      float ms = 1e30f;
+      for (int rep = 0; rep < 2 && rc == QCOLL_OK; ++rep) {
+        hipEventRecord(e0, st);
+        if ((rc = qcoll::launch_eval(p, batch, f, Q, ws, lay, st)) != QCOLL_OK) break;
+        hipEventRecord(e1, st);
+        hipEventSynchronize(e1);
+        float t = 0.f;
+        hipEventElapsedTime(&t, e0, e1);
+        ms = t < ms ? t : ms;
+      }
+      if (rc != QCOLL_OK) break;
       if (ms < best) {
         best = ms;
         bs = sch;

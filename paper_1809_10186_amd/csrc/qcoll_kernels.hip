@@ -623,7 +623,15 @@ Layout make_layout(const Plan &p, int64_t batch, int op) {
   const long cmax = p.chunk > 0 ? p.chunk : 64;
   l.bc = batch < cmax ? (batch > 0 ? batch : 1) : cmax;
   const bool bil = (op == 2);
-  l.pc = 128;
+  // two-pass hot loop: (item, node) pairs per launch such that the launch's
+  // intermediate volume Y (M complex volumes per pair) stays near 192 MiB and
+  // is mostly served from the 256 MiB Infinity Cache when the pencil pass
+  // reads it back (FP64 at N = 32: 32 pairs)
+  {
+    const size_t per_pair = size_t(p.M) * n3 * 2 * es;
+    long pc = long((size_t(192) << 20) / per_pair);
+    l.pc = pc < 8 ? 8 : (pc > 128 ? 128 : pc);
+  }
   if (l.pc > l.bc * p.N_rho) l.pc = l.bc * p.N_rho;
   l.off_h = o; o += al(size_t(l.bc) * n3 * 2 * es);
   l.off_h64 = l.off_h;

@@ -15,9 +15,16 @@ struct Rec {
 };
 
 bool g_on = false;
+std::string g_only;                 // empty: every role is timed
 std::map<std::string, Rec> g_recs;
+std::vector<hipEvent_t> g_pool;     // events of earlier rounds, reused (no create on the launch path)
 
-hipEvent_t make_event() {
+hipEvent_t take_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
   hipEvent_t e = nullptr;
   if (hipEventCreate(&e) != hipSuccess) return nullptr;
   return e;
@@ -28,9 +35,14 @@ hipEvent_t make_event() {
 bool timing_on() { return g_on; }
 
 void timing_begin(const char *name, hipStream_t st) {
+  if (!g_only.empty() && g_only != name) return;
   Rec &r = g_recs[name];
-  hipEvent_t a = make_event(), b = make_event();
-  if (!a || !b) return;
+  hipEvent_t a = take_event(), b = take_event();
+  if (!a || !b) {
+    if (a) g_pool.push_back(a);
+    if (b) g_pool.push_back(b);
+    return;
+  }
   hipEventRecord(a, st);
   r.ev.emplace_back(a, b);
   r.open = r.ev.size();
@@ -52,12 +64,17 @@ qcoll_status qcoll_timing_enable(int32_t on) {
   return QCOLL_OK;
 }
 
+qcoll_status qcoll_timing_select(const char *name) {
+  qcoll::g_only = name ? name : "";
+  return QCOLL_OK;
+}
+
 qcoll_status qcoll_timing_reset(void) {
   for (auto &kv : qcoll::g_recs)
     for (auto &e : kv.second.ev) {
       hipEventSynchronize(e.second);
-      hipEventDestroy(e.first);
-      hipEventDestroy(e.second);
+      qcoll::g_pool.push_back(e.first);
+      qcoll::g_pool.push_back(e.second);
     }
   qcoll::g_recs.clear();
   return QCOLL_OK;
