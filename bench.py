@@ -12,7 +12,12 @@ region records hipEvents around the dominant kernel only (its launch duration
 feeds the roofline entry); the per-kernel breakdown comes from a separate
 five-step pass with every kernel timed.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-acc]
+Outside the headline, "secondary" times the rows that the step does not cover,
+each on its own synthetic workload: the DG weak-form term (MFMA contractions +
+batched Q), the VJP, and the group launches (2D DG batch; uneven three-grid
+batch, forward and VJP).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-acc] [--no-extras]
 """
 import argparse
 import json
@@ -142,6 +147,122 @@ def copy_probe(mib=1024, reps=5):
     print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "reps": reps}))
 
 
+def extras(qc, torch, W, reps=3):
+    """Secondary measurements of the rows outside the headline step, each on its
+    own synthetic workload: the DG weak-form term with the MFMA contractions,
+    the VJP, and the group launches.  Wall time per call after one untimed call."""
+    out = {}
+
+    def timeit(fn, n=reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n * 1e3
+
+    # DG weak form on the 1D DG batch: 64 elements, P = 2 on Gauss nodes (K = 3).
+    # Collocation form T = I, W = diag(w_q) (192 Q evals) and eigen form of the
+    # triple tensor (R = 6 terms per element, 384 Q evals), FP32 + FP64 fix.
+    w = W.WORKLOADS["dg1d_32"]
+    sph = W.sphere_rule(w["M"])
+    plan = qc.Plan(w["N"], w["L"], w["N_rho"], sphere=sph, omega=w["omega"], svd_rank=0, svd_tol=w["svd_tol"],
+                   precision=qc.QCOLL_FP32)
+    E, K = 64, 3
+    F = torch.from_numpy(W.mixture_for("dg1d_32")).to("cuda").reshape(E, K, w["N"], w["N"], w["N"])
+    xg, wg = np.polynomial.legendre.leggauss(K)
+    forms = {"collocation": (np.eye(K), np.diag(wg))}
+    # eigen form of the exact triple tensor of the Lagrange basis on the Gauss nodes
+    xq, wq = np.polynomial.legendre.leggauss(3 * K)
+    ph = np.ones((K, xq.size))
+    for l in range(K):
+        for k in range(K):
+            if k != l:
+                ph[l] *= (xq - xg[k]) / (xg[l] - xg[k])
+    H = np.einsum("q,mq,aq,bq->mab", wq, ph, ph, ph)
+    rows, cols = [], []
+    for m in range(K):
+        lam, U = np.linalg.eigh(H[m])
+        for r in np.nonzero(np.abs(lam) > 1e-13 * np.abs(lam).max())[0]:
+            rows.append(U[:, r])
+            c = np.zeros(K)
+            c[m] = lam[r]
+            cols.append(c)
+    forms["eigen"] = (np.array(rows), np.array(cols).T)
+    for name, (T, Wm) in forms.items():
+        Tg = torch.from_numpy(np.ascontiguousarray(T)).to("cuda")
+        Wg = torch.from_numpy(np.ascontiguousarray(Wm)).to("cuda")
+        Cout = torch.empty_like(F)
+        ms = timeit(lambda: plan.dg_collide(F, Tg, Wg, conserve=True, out=Cout))
+        qc.timing_reset()
+        qc.timing_select("dg contract")
+        qc.timing_enable(True)
+        plan.dg_collide(F, Tg, Wg, conserve=True, out=Cout)
+        qc.timing_enable(False)
+        tc, nc = qc.timing_read().get("dg contract", (0.0, 0))
+        qc.timing_select(None)
+        out[f"dg_collide_{name}"] = {"elements": E, "K": K, "R": int(T.shape[0]), "ms": round(ms, 3),
+                                     "q_evals_per_s": round(E * T.shape[0] / (ms * 1e-3), 1),
+                                     "mfma_contract_ms": round(tc, 4), "mfma_contract_launches": nc}
+    plan.close()
+
+    # VJP (f and omega, through the conservation projection) on 256 items at 32^3
+    w = W.WORKLOADS["adjoint_32"]
+    sph = W.sphere_rule(w["M"])
+    f = torch.from_numpy(W.mixture_for("adjoint_32")).to("cuda")
+    g = torch.from_numpy(W.cotangent(W.mixture_for("adjoint_32"), 4)).to("cuda")
+    for prec, tag in ((qc.QCOLL_FP32, "fp32"), (qc.QCOLL_FP64, "fp64")):
+        pl = qc.Plan(w["N"], w["L"], w["N_rho"], sphere=sph, omega=w["omega"], precision=prec)
+        df = torch.empty_like(f)
+        dw = torch.empty(f.shape[0], dtype=torch.float64, device="cuda")
+        ms = timeit(lambda: pl.vjp(f, g, df=df, domega=dw, through_conserve=True, want_domega=True))
+        out[f"vjp_{tag}"] = {"items": f.shape[0], "ms": round(ms, 3),
+                             "items_per_s": round(f.shape[0] / (ms * 1e-3), 1)}
+        pl.close()
+    del f, g
+
+    # group launches: 2D DG batch (4096 points at 24^3, one plan, autotuned, graph)
+    # and the uneven three-grid batch (2048 points, forward and VJP), FP32 + fix
+    stream = torch.cuda.Stream()
+    w = W.WORKLOADS["dg2d_24"]
+    sph = W.sphere_rule(w["M"])
+    f = torch.from_numpy(W.mixture_for("dg2d_24")).to("cuda")
+    pl = qc.Plan(w["N"], w["L"], w["N_rho"], sphere=sph, omega=w["omega"], precision=qc.QCOLL_FP32)
+    pl.autotune(f)
+    grp = qc.Group([pl], [f.shape[0]])
+    Qs = [torch.empty_like(f)]
+    with torch.cuda.stream(stream):
+        ms = timeit(lambda: grp.eval([f], Qs=Qs, conserve=True, use_graph=True, stream=stream))
+    out["group_dg2d_24"] = {"items": f.shape[0], "ms": round(ms, 3), "evals_per_s": round(f.shape[0] / (ms * 1e-3), 1)}
+    grp.close()
+    pl.close()
+    del f, Qs
+    com = W.UNEVEN_COMMON
+    sph = W.sphere_rule(com["M"])
+    plans, fs, gs = [], [], []
+    for i, gdef in enumerate(W.UNEVEN):
+        plans.append(qc.Plan(gdef["N"], gdef["L"], gdef["N_rho"], sphere=sph, omega=com["omega"], svd_rank=0,
+                             svd_tol=com["svd_tol"], precision=qc.QCOLL_FP32))
+        fi = W.uneven_grid(i)
+        fs.append(torch.from_numpy(fi).to("cuda"))
+        gs.append(torch.from_numpy(W.cotangent(fi, 10 + i)).to("cuda"))
+    grp = qc.Group(plans, [gdef["items"] for gdef in W.UNEVEN])
+    Qs = [torch.empty_like(x) for x in fs]
+    dfs = [torch.empty_like(x) for x in fs]
+    n = sum(gdef["items"] for gdef in W.UNEVEN)
+    with torch.cuda.stream(stream):
+        ms = timeit(lambda: grp.eval(fs, Qs=Qs, conserve=True, use_graph=True, stream=stream))
+        ms_v = timeit(lambda: grp.vjp(fs, gs, dfs=dfs, through_conserve=True, use_graph=True, stream=stream))
+    out["group_uneven"] = {"items": n, "grids": "1024 x 24^3 + 717 x 32^3 + 307 x 48^3",
+                           "eval_ms": round(ms, 3), "evals_per_s": round(n / (ms * 1e-3), 1),
+                           "vjp_ms": round(ms_v, 3), "vjps_per_s": round(n / (ms_v * 1e-3), 1)}
+    grp.close()
+    for pl in plans:
+        pl.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +271,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-acc", action="store_true")
     ap.add_argument("--cpu-items", type=int, default=0)
+    ap.add_argument("--no-extras", action="store_true", help="skip the secondary measurements (DG, VJP, groups)")
     ap.add_argument("--schedule", type=int, default=0, help="hot-loop schedule of the FP32 plan (0 auto)")
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter calibration)")
     a = ap.parse_args()
@@ -228,6 +350,8 @@ def main():
     kernel_ms = {k: round(v[0] / n_brk, 4) for k, v in kt_all.items()}
     Nr, M = w["N_rho"], w["M"]
 
+    extra = None if a.no_extras else extras(qc, torch, W)
+
     acc = None
     cpu = None
     if not a.no_acc or not a.no_cpu:
@@ -274,6 +398,7 @@ def main():
         "rel_linf_err": acc,
         "roofline": roof,
         "kernel_ms_per_step": kernel_ms,
+        "secondary": extra,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -13,7 +13,8 @@ cos x_l cos x_m + sin x_l sin x_m = Re(beta(l) conj(beta(m))).  Then
 Q_j = sum_k Qhat_k exp(2 pi i k.j / N).
 
 Nothing here reuses the transform route of ``spectral`` beyond the forward
-DFT of f: the k-sum is a scatter over explicit index pairs.
+DFT of f: the k-sum is a scatter over explicit index pairs.  For VSS kernels
+the weight alpha_pq(k) of each (p, q) multiplies its own scatter.
 """
 import numpy as np
 from . import dft
@@ -32,19 +33,25 @@ def collide_direct(f, P, g=None):
     kflat = (kk[0] * N + kk[1]) * N + kk[2]
     cc = np.outer(c, cg)
     Qh = np.zeros(n3, dtype=complex)
-    alpha = P.alpha.reshape(P.N_rho, -1)
-    for p, rho in enumerate(P.kt.rho):
-        S = np.zeros((n3, n3))
-        for q in range(P.M):
-            bt = beta(N, P.L, 0.5 * rho * P.sphere_pts[q], P.nyquist).reshape(-1)
-            S += P.sphere_w[q] * np.real(np.outer(bt, np.conj(bt)))
-        t = S * cc
-        acc = (np.bincount(kflat.ravel(), weights=t.real.ravel(), minlength=n3)
-               + 1j * np.bincount(kflat.ravel(), weights=t.imag.ravel(), minlength=n3))
-        Qh += alpha[p] * acc
+    def scatter(t):
+        return (np.bincount(kflat.ravel(), weights=t.real.ravel(), minlength=n3)
+                + 1j * np.bincount(kflat.ravel(), weights=t.imag.ravel(), minlength=n3))
+
+    if P.vss:
+        # sigma-dependent weights: one scatter per (p, q)
+        for p, rho in enumerate(P.kt.rho):
+            for q in range(P.M):
+                bt = beta(N, P.L, 0.5 * rho * P.sphere_pts[q], P.nyquist).reshape(-1)
+                Qh += P.alpha_pq[p, q].reshape(-1) * scatter(np.real(np.outer(bt, np.conj(bt))) * cc)
+    else:
+        alpha = P.alpha.reshape(P.N_rho, -1)
+        for p, rho in enumerate(P.kt.rho):
+            S = np.zeros((n3, n3))
+            for q in range(P.M):
+                bt = beta(N, P.L, 0.5 * rho * P.sphere_pts[q], P.nyquist).reshape(-1)
+                S += P.sphere_w[q] * np.real(np.outer(bt, np.conj(bt)))
+            Qh += alpha[p] * scatter(S * cc)
     lam = P.lam.reshape(-1)
-    t = cc * lam[None, :]
-    Qh -= (np.bincount(kflat.ravel(), weights=t.real.ravel(), minlength=n3)
-           + 1j * np.bincount(kflat.ravel(), weights=t.imag.ravel(), minlength=n3))
+    Qh -= scatter(cc * lam[None, :])
     Q = dft.ifft3(Qh.reshape(N, N, N)) * n3
     return Q.real

@@ -30,6 +30,10 @@ printed; Q is then complex and its real part is returned.
 
 Optional SVD truncation of the gain-weight table alpha_p(k) (rows p) keeps
 singular values above svd_tol times the largest (or the first svd_rank).
+
+VSS kernels (vss_alpha > 1, Section 2): F depends on sigma, so the weights
+alpha_pq(k) = 2 w_p w_q F(k, rho_p, sigma_q) multiply the transform of every
+(p, q) term separately: Q+_k = sum_{p,q} alpha_pq(k) fft3(a a + b b)_k.
 """
 import numpy as np
 from . import dft
@@ -39,14 +43,21 @@ from .kernel import KernelTables, truncate_alpha
 
 class Params:
     def __init__(self, N, L, N_rho, sphere_pts, sphere_w, omega, prefactor=None,
-                 svd_tol=None, svd_rank=None, nyquist="symmetric"):
+                 svd_tol=None, svd_rank=None, nyquist="symmetric", vss_alpha=1.0):
         self.N, self.L = int(N), float(L)
         self.sphere_pts = np.asarray(sphere_pts, dtype=float)
         self.sphere_w = np.asarray(sphere_w, dtype=float)
         self.M = len(self.sphere_w)
         self.nyquist = nyquist
-        self.kt = KernelTables(N, L, N_rho, self.sphere_w, omega, prefactor)
-        self.alpha, self.rank = truncate_alpha(self.kt.alpha, svd_tol, svd_rank)
+        self.vss = float(vss_alpha) != 1.0
+        self.kt = KernelTables(N, L, N_rho, self.sphere_w, omega, prefactor, vss_alpha, self.sphere_pts)
+        if self.vss:
+            if svd_tol or (svd_rank is not None and svd_rank > 0):
+                raise ValueError("no SVD truncation of the VSS weights")
+            self.alpha, self.rank = None, N_rho
+            self.alpha_pq = self.kt.alpha_pq
+        else:
+            self.alpha, self.rank = truncate_alpha(self.kt.alpha, svd_tol, svd_rank)
         self.lam = self.kt.lam
 
     @property
@@ -87,7 +98,24 @@ def gain_terms(f, P):
     return A
 
 
+def gain_vss(f, P):
+    """VSS gain: every (p, q) term transformed and weighted by alpha_pq."""
+    X = dft.fft3(f)
+    Qh = np.zeros(f.shape, dtype=complex)
+    for p, rho in enumerate(P.kt.rho):
+        for q in range(P.M):
+            bt = beta(P.N, P.L, 0.5 * rho * P.sphere_pts[q], P.nyquist)
+            a = dft.ifft3(bt.real * X)
+            b = dft.ifft3(bt.imag * X)
+            Qh += P.alpha_pq[p, q] * dft.fft3(a * a + b * b)
+    return dft.ifft3(Qh)
+
+
 def gain(f, P, A=None):
+    if P.vss:
+        if A is not None:
+            raise ValueError("VSS gain has no per-node accumulators")
+        return gain_vss(f, P)
     if A is None:
         A = gain_terms(f, P)
     Qh = np.zeros(f.shape, dtype=complex)

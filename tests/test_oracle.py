@@ -394,3 +394,95 @@ def test_dg_lgl_basis_ranks():
     ph = dg.lagrange(dg.lgl_nodes(2), x)
     M = np.einsum("q,aq,bq->ab", w, ph, ph)
     assert np.allclose(H.sum(axis=0), M, atol=1e-14)
+
+
+# ---------------------------------------------------------------- VSS kernels (alpha in (1, 2])
+@pytest.mark.parametrize("alpha", [1.3, 1.5, 1.8])
+def test_vss_kernel_mode_reduction(alpha):
+    """F for VSS from the reduced 1-D Gauss-Jacobi integral against direct
+    product-rule quadratures of the defining integral with the symmetrised
+    angular kernel (independent routes): the full sphere around sigma (tight)
+    and the literal half sphere z >= 0 (slowly convergent, loose)."""
+    rng = np.random.Generator(np.random.PCG64(7))
+    for _ in range(4):
+        k = rng.integers(-8, 8, size=3).astype(float)
+        s = rng.normal(size=3)
+        s /= np.linalg.norm(s)
+        rho = float(rng.uniform(0.3, 4.0))
+        b = 0.071
+        F1 = kernel.F_vss(k[None], rho, s, 6.0, 0.74, alpha, b)[0]
+        F2 = kernel.F_vss_sphere(k, rho, s, 6.0, 0.74, alpha, b, axis="sigma")
+        F3 = kernel.F_vss_sphere(k, rho, s, 6.0, 0.74, alpha, b, axis="z", n_theta=400, n_phi=800)
+        assert abs(F1 - F2) <= 1e-10 * abs(F2)
+        assert abs(F1 - F3) <= 2e-7 * abs(F3)
+
+
+@pytest.mark.parametrize("alpha", [1.0, 2.0])
+def test_vss_kernel_mode_reduces_to_vhs(alpha):
+    """At alpha = 1 the angular factor is 1; at alpha = 2 its symmetrised form is
+    ((1+t) + (1-t))/2 = 1: both give the VHS closed form with the same b."""
+    rng = np.random.Generator(np.random.PCG64(8))
+    kv = rng.integers(-10, 10, size=(20, 3)).astype(float)
+    s = rng.normal(size=3)
+    s /= np.linalg.norm(s)
+    F1 = kernel.F_vss(kv, 2.7, s, 6.0, 0.81, alpha, 0.09)
+    F2 = kernel.F_closed(np.linalg.norm(kv, axis=1), 2.7, 6.0, 0.81, 0.09)
+    assert np.abs(F1 - F2).max() <= 1e-13 * np.abs(F2).max()
+    assert kernel.vss_prefactor(0.81, 1.0) == pytest.approx(kernel.vhs_prefactor(0.81), rel=1e-15)
+
+
+def test_vss_alpha2_operator_equals_vhs():
+    """The whole VSS route (one transform and weight per (p, q)) at alpha = 2
+    equals the VHS route (weights collapsed over q) with the same b."""
+    N = 8
+    f = W.maxwellian_mixture(1, N, 4.0, 12, noise=0.2)[0]
+    b = kernel.vhs_prefactor(0.81)
+    Pv = params(N, 4.0, 4, vss_alpha=2.0, prefactor=b)
+    Ph = params(N, 4.0, 4, prefactor=b)
+    Qv = spectral.collide(f, Pv)
+    Qh = spectral.collide(f, Ph)
+    assert np.abs(Qv - Qh).max() < 1e-13 * np.abs(Qh).max()
+
+
+def test_vss_constant_f_has_zero_collisions():
+    P = params(8, 5.0, 6, vss_alpha=1.5)
+    f = np.full((8, 8, 8), 0.37)
+    Q, gp, lp, _ = spectral.collide(f, P, return_parts=True)
+    assert np.abs(Q).max() < 1e-13 * np.abs(lp).max()
+
+
+@pytest.mark.parametrize("N,alpha", [(4, 1.5), (6, 1.3), (8, 1.7)])
+def test_vss_fast_equals_direct_double_sum(N, alpha):
+    f = W.maxwellian_mixture(1, N, 4.0, 13, noise=0.2)[0]
+    P = params(N, 4.0, 4, vss_alpha=alpha)
+    Qs = spectral.collide(f, P)
+    Qd = direct.collide_direct(f, P)
+    assert np.abs(Qs - Qd).max() < 1e-13 * np.abs(Qd).max()
+
+
+def test_vss_maxwellian_is_near_equilibrium_spectrally():
+    """Q(M) = 0 for every collision kernel: the discrete VSS operator on a
+    Maxwellian decays spectrally with N."""
+    rels = []
+    for N in (8, 16, 24):
+        L = 6.0
+        f = W.maxwellian(N, L, 1.0, np.array([0.2, -0.1, 0.3]), 1.0)
+        P = params(N, L, N // 2, vss_alpha=1.5)
+        Q, gp, lp, _ = spectral.collide(f, P, return_parts=True)
+        rels.append(np.abs(Q).max() / np.abs(gp).max())
+    assert rels[0] > 10 * rels[1] > 100 * rels[2]
+    assert rels[2] < 1e-4
+
+
+def test_vss_scaling_translation_and_reflection():
+    N = 8
+    P = params(N, 4.0, 4, M=12, vss_alpha=1.4)
+    f = W.maxwellian_mixture(1, N, 4.0, 14, noise=0.3)[0]
+    Q = spectral.collide(f, P)
+    assert np.abs(spectral.collide(2.5 * f, P) - 6.25 * Q).max() < 1e-12 * 6.25 * np.abs(Q).max()
+    fr = np.roll(f, (2, -1, 3), axis=(0, 1, 2))
+    assert np.abs(spectral.collide(fr, P) - np.roll(Q, (2, -1, 3), axis=(0, 1, 2))).max() < 1e-12 * np.abs(Q).max()
+    # c -> -c (index j -> N-1-j on the cell-centred grid): the weights are even in k
+    fm = f[::-1, ::-1, ::-1]
+    Qm = spectral.collide(fm, P)
+    assert np.abs(Qm - Q[::-1, ::-1, ::-1]).max() < 1e-12 * np.abs(Q).max()
