@@ -355,7 +355,8 @@ def main():
     acc = None
     cpu = None
     if not a.no_acc or not a.no_cpu:
-        n_cpu = a.cpu_items or min(2 * (os.cpu_count() or 1), 16)
+        # about 10-20 s of oracle work: 12 items per host core (one item ~1 s), at most the batch
+        n_cpu = a.cpu_items or min(12 * min(os.cpu_count() or 1, 16), B)
         prm = dict(N=N, L=L, N_rho=Nr, M=M, omega=w["omega"], svd_tol=w["svd_tol"])
         sample = [0, B // 2, B - 1]
         cpu, ref = cpu_baseline(f_np[:max(n_cpu, 1)], prm, n_cpu) if not a.no_cpu else (None, {})

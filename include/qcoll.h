@@ -71,12 +71,20 @@ typedef enum { QCOLL_FP64 = 0, QCOLL_FP32 = 1 } qcoll_precision;
  *              with one point per antipodal pair and weights summing to
  *              2*pi; NULL selects the built-in M = 6 rule (one vertex of each
  *              antipodal pair of the regular icosahedron, weights 2*pi/6).
- *   omega      VHS viscosity index, B = b |g|^{2(1-omega)} (Section 2,
- *              general kernel with alpha = 1); 0.5 <= omega <= 1.
- *   alpha      VSS scattering exponent; only 1 (VHS) is supported.
+ *   omega      viscosity index, B = b |g|^{2(1-omega)} (1 + cos chi)^{alpha-1}
+ *              (Section 2, general kernel); 0.5 <= omega <= 1.
+ *   alpha      VSS scattering exponent, 1 <= alpha <= 2.  alpha = 1 is the VHS
+ *              kernel (kernel modes independent of sigma).  alpha > 1 makes the
+ *              kernel modes F(k, rho_p, sigma_q) depend on the sphere point
+ *              (Appendix, F with the kernel symmetrised in cos chi): every
+ *              (rho_p, sigma_q) term is then transformed forward and weighted
+ *              on its own, about twice the work of alpha = 1.  VSS plans need
+ *              svd_rank < 0; qcoll_vjp, qcoll_eval_bilinear and
+ *              qcoll_dg_collide_svd return ENOTSUP for them.
  *   prefactor  kernel constant b; a value <= 0 or NaN selects the
- *              non-dimensional VHS constant 1/(2^{3-omega} Gamma(2.5-omega) pi)
- *              (Section 2.1); the BKW case uses 1/(4 pi).
+ *              non-dimensional constant alpha / (2^{2-omega+alpha}
+ *              Gamma(2.5-omega) pi) (Section 2.1; 1/(2^{3-omega} Gamma(2.5-omega)
+ *              pi) for VHS); the BKW case uses 1/(4 pi).
  *   svd_rank   truncation of the gain-weight table alpha_p(k) = 2 w_p F(k, rho_p)
  *              (rows p) by its SVD: < 0 keeps the full table exactly (no
  *              SVD); > 0 keeps that many singular triplets; 0 keeps those

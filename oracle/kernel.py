@@ -37,6 +37,15 @@ VSS kernels (Section 2, alpha in (1, 2]):
 * Gain and loss weights keep the quadrature form with the sigma dependence:
   alpha_pq(k) = 2 w_p w_q F(k, rho_p, sigma_q) and
   Lambda(m) = 2 sum_{p,q} w_p w_q F(2m, rho_p, sigma_q).
+* Nyquist index: F now depends on the signs of the components of k, not
+  only on |k|.  Under the symmetric convention (the one that makes the
+  shift factor of the self-paired index the cosine, i.e. the average of the
+  factors at +N/2 and -N/2) every multiplier acts on that index as the
+  average of its values at the two frequencies the index stands for, per
+  axis; so F at an index with Nyquist components is averaged over their
+  signs.  The weights are then even under index reflection, the gain and
+  loss spectra are Hermitian and Q is real.  The literal convention keeps
+  k = -N/2.
 * Non-dimensional constant (Section 2): b = alpha / (2^{2-omega+alpha}
   Gamma(2.5-omega) pi).
 """
@@ -148,7 +157,8 @@ class KernelTables:
     VHS (vss_alpha = 1): alpha[p] = 2 w_p F(k, rho_p).  VSS (vss_alpha > 1):
     alpha_pq[p, q] = 2 w_p w_q F(k, rho_p, sigma_q) (then ``alpha`` is None)."""
 
-    def __init__(self, N, L, N_rho, sphere_w, omega, prefactor=None, vss_alpha=1.0, sphere_pts=None):
+    def __init__(self, N, L, N_rho, sphere_w, omega, prefactor=None, vss_alpha=1.0, sphere_pts=None,
+                 nyquist="symmetric"):
         self.N, self.L, self.N_rho, self.omega = N, float(L), N_rho, float(omega)
         self.vss_alpha = float(vss_alpha)
         self.R = qd.ball_radius(L)
@@ -160,15 +170,29 @@ class KernelTables:
             self.b = vss_prefactor(omega, self.vss_alpha) if prefactor is None else float(prefactor)
             kv = np.stack([k1, k2, k3], axis=-1)
             M = len(sphere_w)
+            nyq = np.abs(kv) == N // 2                 # Nyquist components (k = -N/2)
+            sym = np.any(nyq, axis=-1) if nyquist == "symmetric" else np.zeros(kv.shape[:-1], bool)
+            ksub = kv[sym]
+            nsub = nyq[sym]
+            # the 8 sign patterns, applied to the Nyquist components only
+            flips = [np.where(nsub, 1.0 - 2.0 * np.array(sg, dtype=float), 1.0) for sg in np.ndindex(2, 2, 2)]
+
+            def F_sym(kvecs, sub, rp, sq):
+                # F everywhere, then the sign average of the Nyquist components on the subset
+                F = F_vss(kvecs, rp, sq, L, omega, self.vss_alpha, self.b)
+                if sub.size:
+                    F[sym] = np.mean([F_vss(sub * fl, rp, sq, L, omega, self.vss_alpha, self.b)
+                                      for fl in flips], axis=0)
+                return F
+
             self.alpha = None
             self.alpha_pq = np.zeros((N_rho, M) + self.kabs.shape)
             self.lam_p = np.zeros((N_rho,) + self.kabs.shape)
             for p, (rp, wp) in enumerate(zip(self.rho, self.w_rho)):
                 for q in range(M):
                     sq = sphere_pts[q]
-                    self.alpha_pq[p, q] = 2.0 * wp * sphere_w[q] * F_vss(kv, rp, sq, L, omega, self.vss_alpha, self.b)
-                    self.lam_p[p] += 2.0 * wp * sphere_w[q] * F_vss(2.0 * kv, rp, sq, L, omega, self.vss_alpha,
-                                                                    self.b)
+                    self.alpha_pq[p, q] = 2.0 * wp * sphere_w[q] * F_sym(kv, ksub, rp, sq)
+                    self.lam_p[p] += 2.0 * wp * sphere_w[q] * F_sym(2.0 * kv, 2.0 * ksub, rp, sq)
             self.lam = self.lam_p.sum(axis=0)
             return
         self.b = vhs_prefactor(omega) if prefactor is None else float(prefactor)

@@ -50,7 +50,7 @@ class Params:
         self.M = len(self.sphere_w)
         self.nyquist = nyquist
         self.vss = float(vss_alpha) != 1.0
-        self.kt = KernelTables(N, L, N_rho, self.sphere_w, omega, prefactor, vss_alpha, self.sphere_pts)
+        self.kt = KernelTables(N, L, N_rho, self.sphere_w, omega, prefactor, vss_alpha, self.sphere_pts, nyquist)
         if self.vss:
             if svd_tol or (svd_rank is not None and svd_rank > 0):
                 raise ValueError("no SVD truncation of the VSS weights")

@@ -152,12 +152,13 @@ class Plan:
     """A plan for one velocity grid and kernel.  See include/qcoll.h."""
 
     def __init__(self, N, L, N_rho, sphere=None, omega=1.0, prefactor=None, svd_rank=-1,
-                 svd_tol=0.0, precision=QCOLL_FP64, device=None):
+                 svd_tol=0.0, precision=QCOLL_FP64, device=None, alpha=1.0):
+        """alpha: VSS scattering exponent (1 = VHS; (1, 2] = VSS, full table only)."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("qcoll needs a ROCm GPU")
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
-        p, keep = make_params(N, L, N_rho, sphere, omega, prefactor, svd_rank, svd_tol, precision)
+        p, keep = make_params(N, L, N_rho, sphere, omega, prefactor, svd_rank, svd_tol, precision, alpha)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(lib().qcoll_plan_create(ctypes.byref(p), ctypes.byref(h)))

@@ -61,11 +61,9 @@ qcoll_status qcoll_params_check(const qcoll_params *p) {
   if (p->N_rho < 1) return fail(QCOLL_EINVAL, "N_rho must be >= 1");
   if (p->N_rho > 64) return fail(QCOLL_ENOTSUP, "N_rho must be <= 64");
   if (!(p->omega >= 0.5 && p->omega <= 1.0)) return fail(QCOLL_EINVAL, "omega must lie in [0.5, 1]");
-  if (!(p->alpha == 1.0)) {
-    if (p->alpha > 1.0 && p->alpha <= 2.0)
-      return fail(QCOLL_ENOTSUP, "VSS kernels (alpha in (1, 2]) are not supported; alpha must be 1");
-    return fail(QCOLL_EINVAL, "alpha must be 1 (VHS)");
-  }
+  if (!(p->alpha >= 1.0 && p->alpha <= 2.0)) return fail(QCOLL_EINVAL, "alpha must lie in [1, 2] (1: VHS, > 1: VSS)");
+  if (p->alpha != 1.0 && p->svd_rank >= 0)
+    return fail(QCOLL_ENOTSUP, "VSS plans keep the full kernel-mode table (svd_rank < 0)");
   if (std::isinf(p->prefactor)) return fail(QCOLL_EINVAL, "prefactor must be finite (or NaN/<= 0 for the VHS constant)");
   if (p->precision != QCOLL_FP64 && p->precision != QCOLL_FP32) return fail(QCOLL_EINVAL, "unknown precision");
   if (p->svd_rank == 0 && !(p->svd_tol > 0.0 && p->svd_tol < 1.0))
@@ -149,8 +147,8 @@ qcoll_status qcoll_plan_set_omega(qcoll_plan plan, double omega) {
 qcoll_status qcoll_plan_set_schedule(qcoll_plan plan, int32_t schedule) {
   if (!plan) return fail(QCOLL_EINVAL, "plan is NULL");
   if (schedule < 0 || schedule > 2) return fail(QCOLL_EINVAL, "schedule must be 0, 1 or 2");
-  if (schedule == 2 && !qcoll::fused_gain_supported(plan->p.N, plan->p.precision))
-    return fail(QCOLL_ENOTSUP, "the fused gain kernel needs FP32 and N <= 32");
+  if (schedule == 2 && (!qcoll::fused_gain_supported(plan->p.N, plan->p.precision) || plan->p.is_vss()))
+    return fail(QCOLL_ENOTSUP, "the fused gain kernel needs FP32, N <= 32 and a VHS kernel");
   plan->p.schedule = schedule;
   return QCOLL_OK;
 }
@@ -182,6 +180,7 @@ qcoll_status qcoll_eval_bilinear(qcoll_plan plan, int64_t batch, const double *f
   if (batch < 0) return fail(QCOLL_EINVAL, "batch must be >= 0");
   if (batch == 0) return QCOLL_OK;
   if (!f || !g || !Q) return fail(QCOLL_EINVAL, "f, g and Q must be non-NULL");
+  if (plan->p.is_vss()) return fail(QCOLL_ENOTSUP, "the bilinear Q needs a VHS plan (alpha = 1)");
   const long n3 = plan->p.n3();
   auto overlap = [&](const void *a) {
     return a < (const void *)(Q + batch * n3) && (const void *)Q < (const void *)((const double *)a + batch * n3);
@@ -223,6 +222,7 @@ qcoll_status qcoll_vjp(qcoll_plan plan, int64_t batch, const double *f, const do
   if (batch < 0) return fail(QCOLL_EINVAL, "batch must be >= 0");
   if (batch == 0) return QCOLL_OK;
   if (!f || !g) return fail(QCOLL_EINVAL, "f and g must be non-NULL");
+  if (plan->p.is_vss()) return fail(QCOLL_ENOTSUP, "the VJP needs a VHS plan (alpha = 1)");
   if (!df && !domega) return QCOLL_OK;
   if (domega && plan->p.truncated)
     return fail(QCOLL_ENOTSUP, "the omega gradient needs an untruncated plan (svd_rank < 0)");
@@ -290,6 +290,7 @@ qcoll_status qcoll_dg_collide_svd(qcoll_plan plan, int64_t n_elem, int32_t K, in
   if (K < 1 || K > 64 || R < 1 || R > 4096) return fail(QCOLL_EINVAL, "need 1 <= K <= 64 and 1 <= R <= 4096");
   if (n_elem == 0) return QCOLL_OK;
   if (!T1 || !T2 || !W || !F || !C) return fail(QCOLL_EINVAL, "T1, T2, W, F and C must be non-NULL");
+  if (plan->p.is_vss()) return fail(QCOLL_ENOTSUP, "the bilinear Q needs a VHS plan (alpha = 1)");
   const size_t n3 = size_t(plan->p.n3());
   const size_t terms = size_t(n_elem) * R;
   if (terms > size_t(0x7fffffff)) return fail(QCOLL_EINVAL, "n_elem * R too large");

@@ -229,6 +229,9 @@ qcoll_status qcoll_group_eval(qcoll_group g, const double *const *f, double *con
 qcoll_status qcoll_group_vjp(qcoll_group g, const double *const *f, const double *const *gq, double *const *df,
                              double *const *domega, int32_t through_conserve, void *ws, size_t ws_bytes,
                              void *stream, int32_t use_graph) {
+  if (g)
+    for (size_t i = 0; i < g->plans.size(); ++i)
+      if (g->plans[i]->p.is_vss()) return gfail(QCOLL_ENOTSUP, "the VJP needs VHS plans (alpha = 1)");
   if (g && domega)
     for (size_t i = 0; i < g->plans.size(); ++i)
       if (domega[i] && g->plans[i]->p.truncated)
@@ -266,7 +269,7 @@ size_t qcoll_autotune_workspace_bytes(qcoll_plan plan, int64_t batch) {
   size_t mx = 0;
   for (int sch : {1, 2})
     for (int ck : tune_chunks(batch)) {
-      if (sch == 2 && !qcoll::fused_gain_supported(p.N, p.precision)) continue;
+      if (sch == 2 && (!qcoll::fused_gain_supported(p.N, p.precision) || p.is_vss())) continue;
       p.schedule = sch;
       p.chunk = ck;
       mx = std::max(mx, qcoll::make_layout(p, batch, 0).total);
@@ -319,7 +322,7 @@ qcoll_status qcoll_autotune(qcoll_plan plan, int64_t batch, const double *f, dou
   qcoll_status rc = QCOLL_OK;
   for (int sch : {2, 1})
     for (int ck : tune_chunks(batch)) {
-      if (sch == 2 && !qcoll::fused_gain_supported(p.N, p.precision)) continue;
+      if (sch == 2 && (!qcoll::fused_gain_supported(p.N, p.precision) || p.is_vss())) continue;
       p.schedule = sch;
       p.chunk = ck;
       const qcoll::Layout lay = qcoll::make_layout(p, batch, 0);

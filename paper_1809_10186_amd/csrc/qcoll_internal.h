@@ -17,6 +17,7 @@ struct Plan {
   int N = 0, N_rho = 0, M = 0, rank = 0, precision = 0;
   int nv = 0;                    // rows of V / U the kernels use (rank, or N_rho when the mix saves nothing)
   double L = 0, R = 0, omega = 0, b = 0;
+  double vss = 1.0;              // VSS scattering exponent alpha (1: VHS, sigma-independent kernel modes)
   bool b_follows_omega = true;
   bool truncated = false;        // SVD truncation requested (any svd_rank >= 0)
   bool mix_identity = true;      // B_s = A_s (no SVD rotation)
@@ -34,6 +35,8 @@ struct Plan {
   void *V = nullptr;       // [2*npair][N^3] real: spectral factors of the gain / N^3 (zero-padded row)
   void *lam = nullptr;     // [N^3] loss weights / N^3, always FP64
   void *alpha_eff = nullptr;  // [N_rho][N^3] effective gain weights sum_s U_sp V_s / N^3 (fused schedule)
+  void *alpha_pq = nullptr;   // VSS: [N_rho][M][(N/2+1) N^2] gain weights 2 w_p w_q F(k, rho_p, sigma_q) / N^3,
+                              // planes k1 <= N/2 (the weights are even in k)
   void *umix_d = nullptr;  // [rank][N_rho]
   // FP64 device tables
   double *ginv = nullptr;  // [25] (C C^T)^{-1} of the collision invariants on the grid
@@ -42,6 +45,7 @@ struct Plan {
   int *flag = nullptr;     // non-finite flag
 
   int npair() const { return (nv + 1) / 2; }
+  bool is_vss() const { return vss != 1.0; }
   long n3() const { return long(N) * N * N; }
 };
 

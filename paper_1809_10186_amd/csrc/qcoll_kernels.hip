@@ -175,6 +175,23 @@ __global__ __launch_bounds__(256) void k_sum_nodes(const float4 *__restrict__ W,
   out[b * n_out + o] = acc;
 }
 
+// the same node sum for FP64 spectra: one complex value (16 bytes) per lane
+__global__ __launch_bounds__(256) void k_sum_nodes64(const double2 *__restrict__ W, double2 *__restrict__ out,
+                                                     long nitems, int Nr, long n_in, long n_out) {
+  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nitems * n_in) return;
+  const long b = i / n_in, o = i % n_in;
+  const double2 *w = W + b * Nr * n_in + o;
+  double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 8
+  for (int p = 0; p < Nr; ++p) {
+    const double2 v = w[p * n_in];
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  out[b * n_out + o] = acc;
+}
+
 // Half spectra.  The gain and loss spectra are Hermitian (their inverse
 // transforms are real), so the fused schedule keeps only the planes
 // k1 <= N/2 of each item.  Slab g of such a pass is plane g % (N/2 + 1) of
@@ -319,6 +336,103 @@ struct OpAssembleHalf {
 };
 
 // ----------------------------------------------------------------------------
+// VSS kernels (sigma-dependent kernel modes): every (item, p, q) term is
+// transformed forward and weighted by its own alpha_pq before the sums.
+//
+// Pencil pass over Y[(pair, q)] (after the shifted slab pass): inverse along
+// axis 1, the product t = Re(u)^2 - Im(u)^2 = t1 t2 (the weights w_p w_q sit
+// in alpha_pq), then the forward transform of the real t along axis 1; only
+// the planes k1 <= N/2 are written back (t is real, so its spectrum is
+// Hermitian and the slab pass below needs no other plane).
+template <typename T, int N>
+struct OpGainVss {
+  C<T> *Y;
+  int M;
+  __device__ void operator()(long v, int r) const {
+    constexpr long n2 = long(N) * N, n3 = n2 * N;
+    C<T> *y = Y + v * n3 + r;
+    T xr[N], xi[N];
+    static_for<0, N>([&](auto k) {
+      const C<T> e = y[decltype(k)::value * n2];
+      xr[decltype(k)::value] = e.re;
+      xi[decltype(k)::value] = e.im;
+    });
+    fft_reg<N, +1, T>(xr, xi);
+    static_for<0, N>([&](auto j) {
+      constexpr int jj = decltype(j)::value;
+      const T t = xr[jj] * xr[jj] - xi[jj] * xi[jj];
+      xr[jj] = t;
+      xi[jj] = T(0);
+    });
+    fft_reg<N, -1, T>(xr, xi);
+    static_for<0, N / 2 + 1>([&](auto k) {
+      y[decltype(k)::value * n2] = C<T>{xr[decltype(k)::value], xi[decltype(k)::value]};
+    });
+  }
+};
+
+// Slab accumulation: W[pair] plane k1 (<= N/2) = sum_q alpha_pq(k) fft2(Y[(pair, q)] plane k1)
+// over the (j2, j3) axes.  One workgroup owns SPB planes; lane (s, c) owns column c
+// of plane s (as in the generic slab kernel: column transform from the coalesced
+// loads, row transform through LDS) and keeps that column's sums in registers.
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_vss_acc(const C<T> *Y, const T *apq, C<T> *W, long bp0, long npair, int M,
+                                                 int Nr) {
+  constexpr int SPB = slab_spb<T, N>();
+  constexpr int H1 = N / 2 + 1;
+  constexpr long n2 = long(N) * N, n3 = n2 * N, nh = long(H1) * n2;
+  __shared__ T sre[SPB][N][N + 1];
+  __shared__ T sim[SPB][N][N + 1];
+  const int s = int(threadIdx.x) / N, c = int(threadIdx.x) % N;
+  const long nz = npair * H1;
+  const long z = long(blockIdx.x) * SPB + s;   // (pair, k1) plane
+  const long zl = z < nz ? z : nz - 1;
+  const long pl = zl / H1;
+  const int k1 = int(zl % H1);
+  const int p = int((bp0 + pl) % Nr);
+  T ar[N], ai[N];
+  static_for<0, N>([&](auto k) { ar[decltype(k)::value] = T(0); ai[decltype(k)::value] = T(0); });
+  for (int q = 0; q < M; ++q) {
+    const C<T> *y = Y + (pl * M + q) * n3 + long(k1) * n2 + c;
+    T xr[N], xi[N];
+    static_for<0, N>([&](auto r) {
+      const C<T> v = y[decltype(r)::value * N];
+      xr[decltype(r)::value] = v.re;
+      xi[decltype(r)::value] = v.im;
+    });
+    fft_reg<N, -1, T>(xr, xi);
+    static_for<0, N>([&](auto r) {
+      sre[s][decltype(r)::value][c] = xr[decltype(r)::value];
+      sim[s][decltype(r)::value][c] = xi[decltype(r)::value];
+    });
+    __syncthreads();
+    const int row = c;
+    static_for<0, N>([&](auto k) {
+      xr[decltype(k)::value] = sre[s][row][decltype(k)::value];
+      xi[decltype(k)::value] = sim[s][row][decltype(k)::value];
+    });
+    fft_reg<N, -1, T>(xr, xi);
+    static_for<0, N>([&](auto k) {
+      sre[s][row][decltype(k)::value] = xr[decltype(k)::value];
+      sim[s][row][decltype(k)::value] = xi[decltype(k)::value];
+    });
+    __syncthreads();
+    const T *a = apq + (size_t(p) * M + q) * nh + long(k1) * n2 + c;
+    static_for<0, N>([&](auto r) {
+      constexpr int rr = decltype(r)::value;
+      const T w = a[rr * N];
+      ar[rr] += w * sre[s][rr][c];
+      ai[rr] += w * sim[s][rr][c];
+    });
+    __syncthreads();
+  }
+  if (z < nz) {
+    C<T> *wo = W + pl * nh + long(k1) * n2 + c;
+    static_for<0, N>([&](auto r) { wo[decltype(r)::value * N] = C<T>{ar[decltype(r)::value], ai[decltype(r)::value]}; });
+  }
+}
+
+// ----------------------------------------------------------------------------
 template <typename T, int N>
 struct Engine {
   using P = Passes<T, N>;
@@ -369,6 +483,53 @@ struct Engine {
     return QCOLL_OK;
   }
 
+  // VSS: per (item, node) pair, the shifted slab pass, the pencil pass to the
+  // product and back to the spectrum along axis 1, and the weighted slab
+  // accumulation over q into the pair's half spectrum W; then the node sum and
+  // the half-spectrum tail of the fused schedule.
+  static qcoll_status eval_vss(const Plan &p, const C<T> *H, const C<double> *H64, T *A, C<T> *Y, C<T> *TA,
+                               C<double> *LH, const double *fb, double *Qb, long nb, long pc, hipStream_t st) {
+    constexpr int H1 = N / 2 + 1;
+    constexpr long nh = long(H1) * N * N;
+    constexpr int SPB = slab_spb<T, N>();
+    C<T> *Wp = reinterpret_cast<C<T> *>(A);
+    const long nbp = nb * p.N_rho;
+    const T scale = T(1.0 / double(n3));
+    qcoll_status s;
+    for (long bp0 = 0; bp0 < nbp; bp0 += pc) {
+      const long cnt = (nbp - bp0 < pc) ? (nbp - bp0) : pc;
+      SrcShift<T, N> src{H, reinterpret_cast<const C<T> *>(p.phase), bp0, p.M, p.N_rho, scale};
+      if ((s = slab<SrcShift<T, N>, DstCplx<T, N>, +1>(src, DstCplx<T, N>{Y}, cnt * p.M * N, st, "gain slab")))
+        return s;
+      if ((s = pencil(OpGainVss<T, N>{Y, p.M}, cnt * p.M * N * N, st, "vss pencil"))) return s;
+      TimedLaunch tl("vss acc", st);
+      hipLaunchKernelGGL((k_vss_acc<T, N>), dim3(nblk(cnt * H1, SPB)), dim3(SPB * N), 0, st, Y,
+                         reinterpret_cast<const T *>(p.alpha_pq), Wp + bp0 * nh, bp0, cnt, p.M, p.N_rho);
+      QC_LAUNCH_CHECK("vss acc");
+    }
+    {
+      TimedLaunch tl("sum nodes", st);
+      if constexpr (std::is_same<T, float>::value) {
+        hipLaunchKernelGGL(k_sum_nodes, dim3(nblk(nb * (nh / 2), 256)), dim3(256), 0, st,
+                           reinterpret_cast<const float4 *>(Wp), reinterpret_cast<float4 *>(TA), nb, p.N_rho, nh / 2,
+                           n3 / 2);
+      } else {
+        hipLaunchKernelGGL(k_sum_nodes64, dim3(nblk(nb * nh, 256)), dim3(256), 0, st,
+                           reinterpret_cast<const double2 *>(Wp), reinterpret_cast<double2 *>(TA), nb, p.N_rho, nh,
+                           n3);
+      }
+      QC_LAUNCH_CHECK("sum nodes");
+    }
+    if ((s = slab<SrcCplxHalf<T, N>, DstCplxHalf<T, N>, +1>(SrcCplxHalf<T, N>{TA}, DstCplxHalf<T, N>{TA}, nb * H1, st,
+                                                             "gain inverse slab")))
+      return s;
+    if ((s = Passes<double, N>::template slab<SrcLossHalf<N>, DstCplxHalf<double, N>, +1>(
+             SrcLossHalf<N>{H64, reinterpret_cast<const double *>(p.lam)}, DstCplxHalf<double, N>{LH}, nb * H1, st,
+             "loss slab")))
+      return s;
+    return pencil(OpAssembleHalf<T, N>{TA, LH, fb, Qb}, nb * N * N, st, "assemble");
+  }
+
   // Q(f, f), or the bilinear Q(f, g) when g is non-null (two-pass schedule)
   static qcoll_status eval(const Plan &p, int64_t batch, const double *f, const double *g, double *Q, void *ws,
                            const Layout &lay, hipStream_t st) {
@@ -395,6 +556,10 @@ struct Engine {
         TimedLaunch tl("cast", st);
         hipLaunchKernelGGL(k_cast<T>, dim3(nblk(nb * n3, 256)), dim3(256), 0, st, H64, H, nb * n3);
         QC_LAUNCH_CHECK("cast");
+      }
+      if (p.is_vss()) {
+        if ((s = eval_vss(p, H, H64, A, Y, TA, LH, fb, Q + b0 * n3, nb, lay.pc, st))) return s;
+        continue;
       }
       if (g) {
         // bilinear Q(f, g): gain from both spectra, loss f * ifft(Lambda g^)
@@ -589,7 +754,7 @@ __global__ __launch_bounds__(256) void k_moments(const double *F, double *out, i
 
 // ----------------------------------------------------------------------------
 bool use_fused_gain(const Plan &p) {
-  return p.schedule != 1 && fused_gain_supported(p.N, p.precision);
+  return p.schedule != 1 && !p.is_vss() && fused_gain_supported(p.N, p.precision);
 }
 
 Layout make_layout(const Plan &p, int64_t batch, int op) {
@@ -599,10 +764,13 @@ Layout make_layout(const Plan &p, int64_t batch, int op) {
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   size_t o = 0;
   if (op == 1) {
-    // vjp: items per chunk and per gain sub-chunk (Y holds N_rho*M complex volumes per item)
+    // vjp: items per chunk and per gain sub-chunk (Y holds N_rho*M complex volumes per item).
+    // The adjoint accumulation runs one workgroup per slab pair of the sub-chunk's
+    // items, so the sub-chunk must hold enough items to fill the GPU (32 items at
+    // N = 32: 512 workgroups); Y is capped at 4 GiB.
     l.bc = batch < 32 ? (batch > 0 ? batch : 1) : 32;
     const size_t per_item_y = size_t(p.N_rho) * p.M * n3 * 2 * es;
-    long pc = long((size_t(200) << 20) / per_item_y);
+    long pc = long((size_t(4) << 30) / per_item_y);
     l.pc = pc < 1 ? 1 : (pc > l.bc ? l.bc : pc);
     const size_t c64 = size_t(l.bc) * n3 * 2 * sizeof(double), cT = size_t(l.bc) * n3 * 2 * es;
     l.off_h64 = o; o += al(c64);
@@ -637,11 +805,13 @@ Layout make_layout(const Plan &p, int64_t batch, int op) {
   l.off_h64 = l.off_h;
   if (p.precision == QCOLL_FP32) { l.off_h64 = o; o += al(size_t(l.bc) * n3 * 2 * sizeof(double)); }
   const bool fused = use_fused_gain(p) && !bil;
-  // fused: W, the complex half spectra ((N/2 + 1) N^2 values) of every (item, node)
-  const size_t per_node = fused ? size_t(p.N / 2 + 1) * p.N * p.N * 2 : size_t(n3);
+  const bool vss = p.is_vss();
+  // fused and VSS: W, the complex half spectra ((N/2 + 1) N^2 values) of every (item, node)
+  const bool half = fused || vss;
+  const size_t per_node = half ? size_t(p.N / 2 + 1) * p.N * p.N * 2 : size_t(n3);
   l.off_a = o; o += al(size_t(l.bc) * p.N_rho * per_node * es);
-  l.off_b = o; o += (p.mix_identity || fused) ? 0 : al(size_t(l.bc) * p.nv * n3 * es);
-  l.off_w = o; o += fused ? 0 : al(size_t(l.bc) * p.npair() * n3 * 2 * es);
+  l.off_b = o; o += (p.mix_identity || half) ? 0 : al(size_t(l.bc) * p.nv * n3 * es);
+  l.off_w = o; o += half ? 0 : al(size_t(l.bc) * p.npair() * n3 * 2 * es);
   l.off_t = o; o += al(size_t(l.bc) * n3 * 2 * es);
   l.off_l = o; o += al(size_t(l.bc) * n3 * 2 * sizeof(double));
   l.off_y = o; o += fused ? 0 : al(size_t(l.pc) * p.M * n3 * 2 * es);

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 #include "qcoll_internal.h"
 
@@ -297,6 +298,171 @@ static qcoll_status upload_truncated(Plan &p, int svd_rank, double svd_tol) {
   return upload_alpha_eff(p, Vs, U);
 }
 
+// ---------------------------------------------------------------------------
+// VSS kernel modes (Section 2 kernel with alpha in (1, 2]; Appendix definition
+// of F with the kernel symmetrised in cos chi), by the Funk-Hecke formula.
+// With A(t) = ((1+t)^{alpha-1} + (1-t)^{alpha-1}) / 2 and a = pi rho |k| / (2L):
+//   F(k, rho, sigma) = 2 rho^2 b rho^{2(1-omega)} int_{S^2+} A(sigma.c) cos(a k^.c) dc
+//                    = b rho^{4-2 omega} int_{S^2} A(sigma.c) cos(a k^.c) dc      (even in c).
+// The plane wave is sum_n (2n+1) i^n j_n(a) P_n(k^.c); Funk-Hecke turns
+// int_{S^2} A(sigma.c) P_n(k^.c) dc into 2 pi (int_{-1}^{1} A P_n dt) P_n(sigma.k^);
+// A is even, so only even n remain and int A P_n = c_n := int (1-t)^{alpha-1} P_n dt:
+//   F = 2 pi b rho^{4-2 omega} sum_{n even} (2n+1) (-1)^{n/2} c_n j_n(a) P_n(sigma.k^),
+// with c_0 = 2^alpha / alpha and c_n = -c_{n-1} (alpha - n) / (alpha + n).  For
+// alpha = 1 (or 2) only c_0 survives among even n and F is the VHS closed form.
+
+// j_0..j_nmax(a) by downward recurrence from well above nmax, normalised by
+// sum_n (2n+1) j_n(a)^2 = 1 and signed by the larger of j_0, j_1 in closed form.
+static void sph_bessel(double a, int nmax, std::vector<double> &j, std::vector<double> &t) {
+  j.assign(nmax + 1, 0.0);
+  if (a == 0.0) {
+    j[0] = 1.0;
+    return;
+  }
+  const int nst = std::max(nmax, int(a)) + 60;
+  t.assign(nst + 2, 0.0);
+  t[nst] = 1e-30;
+  for (int n = nst; n >= 1; --n) {
+    t[n - 1] = (2.0 * n + 1.0) / a * t[n] - t[n + 1];
+    if (std::fabs(t[n - 1]) > 1e100)
+      for (int k = n - 1; k <= nst; ++k) t[k] *= 1e-100;
+  }
+  // normalise relative to the largest value (neither the squares nor their sum
+  // can overflow or underflow)
+  double tmax = 0.0;
+  for (int n = 0; n <= nst; ++n) tmax = std::max(tmax, std::fabs(t[n]));
+  double s = 0.0;
+  for (int n = nst; n >= 0; --n) {
+    const double u = t[n] / tmax;
+    s += (2.0 * n + 1.0) * u * u;
+  }
+  double scale = 1.0 / (tmax * std::sqrt(s));
+  const double j0 = std::sin(a) / a, j1 = std::sin(a) / (a * a) - std::cos(a) / a;
+  if (std::fabs(j0) >= std::fabs(j1)) {
+    if ((j0 < 0) != (t[0] < 0)) scale = -scale;
+  } else if ((j1 < 0) != (t[1] < 0)) {
+    scale = -scale;
+  }
+  for (int n = 0; n <= nmax; ++n) j[n] = t[n] * scale;
+}
+
+// terms needed for |k| with argument a: j_n(a) is negligible past a + O(a^{1/3})
+static int vss_nmax(double a) { return (int(a + 10.0 * std::cbrt(a) + 30.0) / 2) * 2; }
+
+// F / (b rho^{4-2 omega}) for the given direction cosines mu_q = sigma_q . k^
+static void vss_modes(double a, const double *mu, int nq, const std::vector<double> &coef, double *out,
+                      std::vector<double> &jn, std::vector<double> &tmp) {
+  const int nmax = std::min(vss_nmax(a), int(coef.size()) - 1);
+  sph_bessel(a, nmax, jn, tmp);
+  for (int q = 0; q < nq; ++q) {
+    const double m = mu[q];
+    double p0 = 1.0, p1 = m, acc = coef[0] * jn[0];
+    for (int n = 2; n <= nmax; n += 2) {
+      // advance P_{n-1}, P_n by the three-term recurrence
+      const double p2 = ((2.0 * (n - 1) + 1.0) * m * p1 - (n - 1) * p0) / n;
+      acc += coef[n] * jn[n] * p2;
+      const double p3 = ((2.0 * n + 1.0) * m * p2 - n * p1) / (n + 1);
+      p0 = p2;
+      p1 = p3;
+    }
+    out[q] = acc;
+  }
+}
+
+// alpha_pq half tables (T precision, / N^3) and Lambda (FP64, / N^3) for a VSS plan
+static qcoll_status upload_vss_tables(Plan &p) {
+  const int N = p.N, Nr = p.N_rho, M = p.M, H1 = N / 2 + 1;
+  const long n2 = long(N) * N, n3 = p.n3(), nh = long(H1) * n2;
+  const double alpha = p.vss;
+  // coefficient of n in the series: 2 pi (2n+1) (-1)^{n/2} c_n (even n; odd entries unused)
+  double amax = 0.0;
+  for (int r = 0; r < Nr; ++r) amax = std::max(amax, kPiD * p.rho[r] * std::sqrt(3.0) * (N / 2) / p.L);
+  const int ncoef = vss_nmax(amax) + 2;
+  std::vector<double> cn(ncoef + 1), coef(ncoef + 1, 0.0);
+  cn[0] = std::pow(2.0, alpha) / alpha;
+  for (int n = 1; n <= ncoef; ++n) cn[n] = -cn[n - 1] * (alpha - n) / (alpha + n);
+  for (int n = 0; n <= ncoef; n += 2) coef[n] = 2.0 * kPiD * (2.0 * n + 1.0) * ((n / 2) % 2 ? -1.0 : 1.0) * cn[n];
+  std::vector<double> apq(size_t(Nr) * M * nh, 0.0), lam_p(size_t(Nr) * n3, 0.0);
+  const double inv = 1.0 / double(n3);
+  // The self-paired index N/2 of an axis stands for the frequencies +-N/2: a
+  // multiplier acts on it as the average of its two values (for the shift
+  // factor this is the cosine rule of the plan's phase tables).  F depends on
+  // the signs of the components through k^.sigma, so at indices with Nyquist
+  // components it is averaged over their sign patterns; the weights are then
+  // even under index reflection and the gain and loss spectra Hermitian.
+  auto work = [&](int r) {
+    const double rr = p.rho[r], wr = p.w_rho[r];
+    const double c = p.b * std::pow(rr, 4.0 - 2.0 * p.omega);
+    std::vector<double> mu(M), fq(M), acc(M), jn, tmp;
+    for (long idx = 0; idx < n3; ++idx) {
+      const int i = int(idx / n2), jj = int((idx / N) % N), kk = int(idx % N);
+      const double k1 = kappa(i, N), k2 = kappa(jj, N), k3 = kappa(kk, N);
+      const double ka = std::sqrt(k1 * k1 + k2 * k2 + k3 * k3);
+      const bool nq1 = (i == N / 2), nq2 = (jj == N / 2), nq3 = (kk == N / 2);
+      const int npat = (nq1 || nq2 || nq3) ? 8 : 1;
+      // acc[q] = F(arg a, k^.sigma_q) / (b rho^{4-2 omega}), sign-averaged
+      auto modes = [&](double a) {
+        std::fill(acc.begin(), acc.end(), 0.0);
+        for (int sg = 0; sg < npat; ++sg) {
+          const double x1 = (nq1 && (sg & 1)) ? -k1 : k1;
+          const double x2 = (nq2 && (sg & 2)) ? -k2 : k2;
+          const double x3 = (nq3 && (sg & 4)) ? -k3 : k3;
+          for (int q = 0; q < M; ++q) {
+            const double *sv = &p.sphere[4 * q];
+            mu[q] = ka > 0 ? std::max(-1.0, std::min(1.0, (x1 * sv[0] + x2 * sv[1] + x3 * sv[2]) / ka)) : 1.0;
+          }
+          vss_modes(a, mu.data(), M, coef, fq.data(), jn, tmp);
+          for (int q = 0; q < M; ++q) acc[q] += fq[q] / npat;
+        }
+      };
+      // loss: Lambda_p(k) = sum_q 2 w_p w_q F(2k, rho_p, sigma_q)
+      modes(kPiD * rr * ka / p.L);
+      double lp = 0.0;
+      for (int q = 0; q < M; ++q) lp += 2.0 * wr * p.sphere[4 * q + 3] * c * acc[q];
+      lam_p[size_t(r) * n3 + idx] = lp;
+      // gain on the planes k1 <= N/2: 2 w_p w_q F(k, rho_p, sigma_q) / N^3
+      if (i < H1) {
+        modes(kPiD * rr * ka / (2.0 * p.L));
+        for (int q = 0; q < M; ++q)
+          apq[(size_t(r) * M + q) * nh + idx] = 2.0 * wr * p.sphere[4 * q + 3] * c * acc[q] * inv;
+      }
+    }
+  };
+  // radial nodes over host threads; each node writes only its own rows
+  const int nth = std::max(1, std::min(Nr, int(std::thread::hardware_concurrency())));
+  std::vector<std::thread> th;
+  int started = 0;
+  try {
+    for (int t = 0; t < nth; ++t) {
+      th.emplace_back([&, t] {
+        for (int r = t; r < Nr; r += nth) work(r);
+      });
+      ++started;
+    }
+  } catch (...) {
+    // no more threads: the nodes of the threads that did not start run here
+  }
+  for (int t = started; t < nth; ++t)
+    for (int r = t; r < Nr; r += nth) work(r);
+  for (auto &x : th) x.join();
+  std::vector<double> lam(n3, 0.0);
+  for (int r = 0; r < Nr; ++r)
+    for (long k = 0; k < n3; ++k) lam[k] += lam_p[size_t(r) * n3 + k];
+  for (auto &x : lam) x *= inv;
+  p.truncated = false;
+  p.mix_identity = true;
+  p.rank = p.nv = Nr;
+  p.sigma_max = p.sigma_min_kept = 0.0;
+  qcoll_status st;
+  if ((st = upload<double>(lam, &p.lam)) != QCOLL_OK) return st;
+  return p.precision == QCOLL_FP32 ? upload<float>(apq, &p.alpha_pq) : upload<double>(apq, &p.alpha_pq);
+}
+
+static double kernel_constant(double omega, double alpha) {
+  // non-dimensional VSS constant alpha / (2^{2-omega+alpha} Gamma(2.5-omega) pi) (Section 2)
+  return alpha / (std::pow(2.0, 2.0 - omega + alpha) * std::tgamma(2.5 - omega) * kPiD);
+}
+
 static void free_kernel_tables(Plan &p) {
   hipFree(p.V);
   hipFree(p.lam);
@@ -304,7 +470,8 @@ static void free_kernel_tables(Plan &p) {
   hipFree(p.lam_p);
   hipFree(p.dlog);
   hipFree(p.alpha_eff);
-  p.alpha_eff = nullptr;
+  hipFree(p.alpha_pq);
+  p.alpha_eff = p.alpha_pq = nullptr;
   p.V = p.lam = p.umix_d = nullptr;
   p.lam_p = p.dlog = nullptr;
 }
@@ -315,9 +482,9 @@ qcoll_status plan_build(Plan &p, const qcoll_params &prm) {
   p.N_rho = prm.N_rho;
   p.omega = prm.omega;
   p.precision = prm.precision;
+  p.vss = prm.alpha;
   p.b_follows_omega = !(prm.prefactor > 0.0);
-  p.b = p.b_follows_omega ? 1.0 / (std::pow(2.0, 3.0 - p.omega) * std::tgamma(2.5 - p.omega) * kPiD)
-                          : prm.prefactor;
+  p.b = p.b_follows_omega ? kernel_constant(p.omega, p.vss) : prm.prefactor;
   p.R = 4.0 * p.L / (3.0 + std::sqrt(2.0));
   gauss_legendre(p.N_rho, 0.0, p.R, p.rho, p.w_rho);
   if (prm.sphere) {
@@ -400,6 +567,7 @@ qcoll_status plan_build(Plan &p, const qcoll_params &prm) {
     set_error("hipMemset failed");
     return QCOLL_EDEVICE;
   }
+  if (p.is_vss()) return upload_vss_tables(p);
   if (prm.svd_rank < 0) return upload_kernel_tables(p);
   return upload_truncated(p, prm.svd_rank, prm.svd_tol);
 }
@@ -415,9 +583,8 @@ qcoll_status plan_set_omega(Plan &p, double omega) {
   }
   free_kernel_tables(p);
   p.omega = omega;
-  if (p.b_follows_omega)
-    p.b = 1.0 / (std::pow(2.0, 3.0 - p.omega) * std::tgamma(2.5 - p.omega) * kPiD);
-  return upload_kernel_tables(p);
+  if (p.b_follows_omega) p.b = kernel_constant(p.omega, p.vss);
+  return p.is_vss() ? upload_vss_tables(p) : upload_kernel_tables(p);
 }
 
 void plan_free(Plan &p) {

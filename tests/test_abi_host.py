@@ -47,6 +47,8 @@ def test_valid_params_pass():
     assert qc.params_check(**ok_kw(svd_rank=0, svd_tol=1e-8))[0] == 0
     for N in (8, 12, 24, 32, 48):
         assert qc.params_check(**ok_kw(N=N))[0] == 0
+    for a in (1.2, 1.5, 2.0):    # VSS kernels with the full table
+        assert qc.params_check(**ok_kw(alpha=a))[0] == 0
 
 
 @pytest.mark.parametrize("over,code,frag", [
@@ -54,7 +56,8 @@ def test_valid_params_pass():
     (dict(L=0.0), 1, "L"), (dict(L=float("nan")), 1, "L"), (dict(L=-1.0), 1, "L"),
     (dict(N_rho=0), 1, "N_rho"), (dict(N_rho=65), 2, "N_rho"),
     (dict(omega=0.4), 1, "omega"), (dict(omega=1.2), 1, "omega"),
-    (dict(alpha=1.5), 2, "VSS"), (dict(alpha=3.0), 1, "alpha"),
+    (dict(alpha=1.5, svd_rank=0, svd_tol=1e-8), 2, "VSS"), (dict(alpha=3.0), 1, "alpha"),
+    (dict(alpha=0.9), 1, "alpha"),
     (dict(precision=7), 1, "precision"),
     (dict(svd_rank=0, svd_tol=0.0), 1, "svd_tol"), (dict(svd_rank=99), 1, "svd_rank"),
     (dict(prefactor=float("inf")), 1, "prefactor"),

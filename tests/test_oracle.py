@@ -486,3 +486,19 @@ def test_vss_scaling_translation_and_reflection():
     fm = f[::-1, ::-1, ::-1]
     Qm = spectral.collide(fm, P)
     assert np.abs(Qm - Q[::-1, ::-1, ::-1]).max() < 1e-12 * np.abs(Q).max()
+
+
+def test_vss_symmetric_nyquist_weights_are_even_and_q_real():
+    """Reading of the self-paired Nyquist index for sigma-dependent modes: the
+    sign average makes the weights even under index reflection (so the gain and
+    loss spectra are Hermitian and Q is real); the literal k = -N/2 does not."""
+    N = 8
+    f = W.maxwellian_mixture(1, N, 4.0, 15, noise=0.2)[0]
+    P = params(N, 4.0, 4, M=12, vss_alpha=1.5)
+    refl = lambda a: np.roll(a[..., ::-1, ::-1, ::-1], 1, axis=(-3, -2, -1))   # index n -> -n mod N
+    assert np.abs(P.alpha_pq - refl(P.alpha_pq)).max() <= 1e-15 * np.abs(P.alpha_pq).max()
+    assert np.abs(P.lam - refl(P.lam)).max() <= 1e-15 * np.abs(P.lam).max()
+    Q, gp, lp, Qi = spectral.collide(f, P, return_parts=True)
+    assert np.abs(Qi).max() <= 1e-14 * np.abs(Q).max()
+    Pl = params(N, 4.0, 4, M=12, vss_alpha=1.5, nyquist="literal")
+    assert np.abs(Pl.alpha_pq - refl(Pl.alpha_pq)).max() > 1e-6 * np.abs(Pl.alpha_pq).max()
