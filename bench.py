@@ -14,8 +14,8 @@ five-step pass with every kernel timed.
 
 Outside the headline, "secondary" times the rows that the step does not cover,
 each on its own synthetic workload: the DG weak-form term (MFMA contractions +
-batched Q), the VJP, and the group launches (2D DG batch; uneven three-grid
-batch, forward and VJP).
+batched Q), a VSS kernel (alpha = 1.5) on the same batch, the VJP, and the
+group launches (2D DG batch; uneven three-grid batch, forward and VJP).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-acc] [--no-extras]
 """
@@ -206,6 +206,24 @@ def extras(qc, torch, W, reps=3):
                                      "q_evals_per_s": round(E * T.shape[0] / (ms * 1e-3), 1),
                                      "mfma_contract_ms": round(tc, 4), "mfma_contract_launches": nc}
     plan.close()
+
+    # VSS kernel (alpha = 1.5, sigma-dependent kernel modes) on the 1D DG batch, eval + conserve
+    w = W.WORKLOADS["dg1d_32"]
+    sph = W.sphere_rule(w["M"])
+    f = torch.from_numpy(W.mixture_for("dg1d_32")).to("cuda")
+    Qv = torch.empty_like(f)
+    for prec, tag in ((qc.QCOLL_FP32, "fp32"), (qc.QCOLL_FP64, "fp64")):
+        pl = qc.Plan(w["N"], w["L"], w["N_rho"], sphere=sph, omega=w["omega"], precision=prec, alpha=1.5)
+        pl.autotune(f, Qv)
+
+        def vss_step():
+            pl.eval(f, Qv)
+            pl.conserve(Qv)
+        ms = timeit(vss_step)
+        out[f"vss_alpha1.5_{tag}"] = {"items": f.shape[0], "ms": round(ms, 3),
+                                      "evals_per_s": round(f.shape[0] / (ms * 1e-3), 1)}
+        pl.close()
+    del f, Qv
 
     # VJP (f and omega, through the conservation projection) on 256 items at 32^3
     w = W.WORKLOADS["adjoint_32"]
