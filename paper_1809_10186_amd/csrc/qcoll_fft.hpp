@@ -141,6 +141,67 @@ __device__ __forceinline__ void twiddle(T &a, T &b) {
   }
 }
 
+// Twiddle split for the factored radix-4 combine: w = exp(SIGN 2 pi i E / N) =
+// f (1 + i tau) with f = cos (|cos| >= |sin|), or w = f (kap + i) with f = sin
+// otherwise, so that w x = f x' where x' costs two FMAs and f folds into the
+// butterfly's own FMAs.  Trivial twiddles (multiples of pi/2) are exact moves.
+template <int N, int E, int SIGN>
+struct TwSplit {
+  static constexpr int e = ((E % N) + N) % N;
+  static constexpr bool trivial = (e == 0) || (4 * e == N) || (2 * e == N) || (4 * e == 3 * N);
+  static constexpr SinCos w = sincos_2pi(e, N);
+  static constexpr double c = w.c, s = SIGN * w.s;
+  static constexpr bool by_cos = (c >= 0 ? c : -c) >= (s >= 0 ? s : -s);
+  static constexpr double f = by_cos ? c : s;
+  static constexpr double r = by_cos ? s / c : c / s;   // tau or kap
+};
+
+// x' with w x = f x': by cosine, x' = (a - tau b, b + tau a); by sine, x' = (kap a - b, a + kap b)
+template <int N, int E, int SIGN, typename T>
+__device__ __forceinline__ void twiddle_reduced(T &a, T &b) {
+  using W = TwSplit<N, E, SIGN>;
+  constexpr T r = T(W::r);
+  if constexpr (W::by_cos) {
+    const T na = a - r * b, nb = b + r * a;
+    a = na;
+    b = nb;
+  } else {
+    const T na = r * a - b, nb = a + r * b;
+    a = na;
+    b = nb;
+  }
+}
+
+// Radix-4 combine of output column k: inputs x_i (i = 0..3) of the sub-transforms,
+// twiddles w_i = exp(SIGN 2 pi i (i k) / N), then the 4-point DFT.  With
+// w_i x_i = f_i x_i', the sums x0 +- w2 x2 and w1 x1 +- w3 x3 take the factors f_i
+// as FMA multipliers; trivial twiddles keep the plain moves.
+template <int N, int K, int SIGN, typename T>
+__device__ __forceinline__ void combine4(T *xr, T *xi) {
+  using W1 = TwSplit<N, K, SIGN>;
+  using W2 = TwSplit<N, 2 * K, SIGN>;
+  using W3 = TwSplit<N, 3 * K, SIGN>;
+  T f1 = T(1), f2 = T(1), f3 = T(1);
+  if constexpr (W1::trivial) twiddle<N, K, SIGN, T>(xr[1], xi[1]);
+  else { twiddle_reduced<N, K, SIGN, T>(xr[1], xi[1]); f1 = T(W1::f); }
+  if constexpr (W2::trivial) twiddle<N, 2 * K, SIGN, T>(xr[2], xi[2]);
+  else { twiddle_reduced<N, 2 * K, SIGN, T>(xr[2], xi[2]); f2 = T(W2::f); }
+  if constexpr (W3::trivial) twiddle<N, 3 * K, SIGN, T>(xr[3], xi[3]);
+  else { twiddle_reduced<N, 3 * K, SIGN, T>(xr[3], xi[3]); f3 = T(W3::f); }
+  const T s02r = xr[0] + f2 * xr[2], s02i = xi[0] + f2 * xi[2];
+  const T d02r = xr[0] - f2 * xr[2], d02i = xi[0] - f2 * xi[2];
+  const T y3r = f3 * xr[3], y3i = f3 * xi[3];
+  const T s13r = f1 * xr[1] + y3r, s13i = f1 * xi[1] + y3i;
+  const T d13r = f1 * xr[1] - y3r, d13i = f1 * xi[1] - y3i;
+  // (SIGN i) * d13
+  const T wr = (SIGN > 0) ? -d13i : d13i;
+  const T wi = (SIGN > 0) ? d13r : -d13r;
+  xr[0] = s02r + s13r; xi[0] = s02i + s13i;
+  xr[2] = s02r - s13r; xi[2] = s02i - s13i;
+  xr[1] = d02r + wr;   xi[1] = d02i + wi;
+  xr[3] = d02r - wr;   xi[3] = d02i - wi;
+}
+
 template <int N, int SIGN, typename T>
 __device__ __forceinline__ void fft_reg(T *re, T *im) {
   if constexpr (N == 1) {
@@ -164,9 +225,16 @@ __device__ __forceinline__ void fft_reg(T *re, T *im) {
         constexpr int ii = decltype(i)::value;
         xr[ii] = sr[ii][kk];
         xi[ii] = si[ii][kk];
-        twiddle<N, ii * kk, SIGN, T>(xr[ii], xi[ii]);
       });
-      small_dft<R, SIGN, T>(xr, xi);
+      if constexpr (R == 4) {
+        combine4<N, kk, SIGN, T>(xr, xi);
+      } else {
+        static_for<0, R>([&](auto i) {
+          constexpr int ii = decltype(i)::value;
+          twiddle<N, ii * kk, SIGN, T>(xr[ii], xi[ii]);
+        });
+        small_dft<R, SIGN, T>(xr, xi);
+      }
       static_for<0, R>([&](auto t) {
         re[kk + M * decltype(t)::value] = xr[decltype(t)::value];
         im[kk + M * decltype(t)::value] = xi[decltype(t)::value];
