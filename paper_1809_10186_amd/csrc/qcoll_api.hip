@@ -321,7 +321,7 @@ qcoll_status qcoll_poll(qcoll_plan plan) {
   if (hipMemcpy(&h, plan->p.flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
     return fail(QCOLL_EDEVICE, "hipMemcpy failed");
   if (h) {
-    hipMemset(plan->p.flag, 0, sizeof(int));
+    if (hipMemset(plan->p.flag, 0, sizeof(int)) != hipSuccess) return fail(QCOLL_EDEVICE, "hipMemset failed");
     return fail(QCOLL_ENONFINITE, "a non-finite value reached the moment sums");
   }
   return QCOLL_OK;

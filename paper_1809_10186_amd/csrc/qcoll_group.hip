@@ -142,12 +142,12 @@ qcoll_status run(qcoll_group g, int32_t op, const double *const *a, const double
   if (ec != hipSuccess || !graph) return gfail(QCOLL_EDEVICE, "hipStreamEndCapture failed");
   hipGraphExec_t exec = nullptr;
   if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     return gfail(QCOLL_EDEVICE, "hipGraphInstantiate failed");
   }
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   if (g->cache.size() >= 8) {
-    hipGraphExecDestroy(g->cache.front().exec);
+    (void)hipGraphExecDestroy(g->cache.front().exec);
     g->cache.erase(g->cache.begin());
   }
   qcoll_group_s::Cached c;
@@ -330,12 +330,14 @@ qcoll_status qcoll_autotune(qcoll_plan plan, int64_t batch, const double *f, dou
       // best of two timed runs
       float ms = 1e30f;
       for (int rep = 0; rep < 2 && rc == QCOLL_OK; ++rep) {
-        hipEventRecord(e0, st);
+        if (hipEventRecord(e0, st) != hipSuccess) { rc = gfail(QCOLL_EDEVICE, "hipEventRecord failed"); break; }
         if ((rc = qcoll::launch_eval(p, batch, f, Q, ws, lay, st)) != QCOLL_OK) break;
-        hipEventRecord(e1, st);
-        hipEventSynchronize(e1);
         float t = 0.f;
-        hipEventElapsedTime(&t, e0, e1);
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+          rc = gfail(QCOLL_EDEVICE, "autotune timing events failed");
+          break;
+        }
         ms = t < ms ? t : ms;
       }
       if (rc != QCOLL_OK) break;
@@ -346,8 +348,8 @@ qcoll_status qcoll_autotune(qcoll_plan plan, int64_t batch, const double *f, dou
       }
     }
   qcoll_timing_enable(timing);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (rc != QCOLL_OK) return rc;
   p.schedule = bs;
   p.chunk = bc;

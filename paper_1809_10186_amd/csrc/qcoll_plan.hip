@@ -464,13 +464,13 @@ static double kernel_constant(double omega, double alpha) {
 }
 
 static void free_kernel_tables(Plan &p) {
-  hipFree(p.V);
-  hipFree(p.lam);
-  hipFree(p.umix_d);
-  hipFree(p.lam_p);
-  hipFree(p.dlog);
-  hipFree(p.alpha_eff);
-  hipFree(p.alpha_pq);
+  (void)hipFree(p.V);
+  (void)hipFree(p.lam);
+  (void)hipFree(p.umix_d);
+  (void)hipFree(p.lam_p);
+  (void)hipFree(p.dlog);
+  (void)hipFree(p.alpha_eff);
+  (void)hipFree(p.alpha_pq);
   p.alpha_eff = p.alpha_pq = nullptr;
   p.V = p.lam = p.umix_d = nullptr;
   p.lam_p = p.dlog = nullptr;
@@ -589,10 +589,10 @@ qcoll_status plan_set_omega(Plan &p, double omega) {
 
 void plan_free(Plan &p) {
   free_kernel_tables(p);
-  hipFree(p.phase);
-  hipFree(p.wq);
-  hipFree(p.ginv);
-  hipFree(p.flag);
+  (void)hipFree(p.phase);
+  (void)hipFree(p.wq);
+  (void)hipFree(p.ginv);
+  (void)hipFree(p.flag);
   p.phase = p.wq = nullptr;
   p.ginv = nullptr;
   p.flag = nullptr;

@@ -43,7 +43,11 @@ void timing_begin(const char *name, hipStream_t st) {
     if (b) g_pool.push_back(b);
     return;
   }
-  hipEventRecord(a, st);
+  if (hipEventRecord(a, st) != hipSuccess) {
+    g_pool.push_back(a);
+    g_pool.push_back(b);
+    return;
+  }
   r.ev.emplace_back(a, b);
   r.open = r.ev.size();
 }
@@ -51,7 +55,7 @@ void timing_begin(const char *name, hipStream_t st) {
 void timing_end(const char *name, hipStream_t st) {
   auto it = g_recs.find(name);
   if (it == g_recs.end() || it->second.open == 0) return;
-  hipEventRecord(it->second.ev[it->second.open - 1].second, st);
+  (void)hipEventRecord(it->second.ev[it->second.open - 1].second, st);
   it->second.open = 0;
 }
 
@@ -72,7 +76,7 @@ qcoll_status qcoll_timing_select(const char *name) {
 qcoll_status qcoll_timing_reset(void) {
   for (auto &kv : qcoll::g_recs)
     for (auto &e : kv.second.ev) {
-      hipEventSynchronize(e.second);
+      (void)hipEventSynchronize(e.second);
       qcoll::g_pool.push_back(e.first);
       qcoll::g_pool.push_back(e.second);
     }
