@@ -502,3 +502,78 @@ def test_vss_symmetric_nyquist_weights_are_even_and_q_real():
     assert np.abs(Qi).max() <= 1e-14 * np.abs(Q).max()
     Pl = params(N, 4.0, 4, M=12, vss_alpha=1.5, nyquist="literal")
     assert np.abs(Pl.alpha_pq - refl(Pl.alpha_pq)).max() > 1e-6 * np.abs(Pl.alpha_pq).max()
+
+
+# ---------------------------------------------------------------- 1-D RKDG driver (Section 3)
+def _dg1d(I, P, N=4, L=4.0, inv_kn=0.0, left=None, right=None, coll="collocation", faces=None, M=6):
+    from oracle import rkdg
+    left = left or rkdg.Bc("periodic")
+    right = right or rkdg.Bc("periodic")
+    faces = np.linspace(0.0, 1.0, I + 1) if faces is None else faces
+    return rkdg.Dg1d(faces, P, params(N, L, 2, M=M), inv_kn, left, right, coll=coll)
+
+
+def test_rkdg_summation_by_parts():
+    """S + S^T = phi(1) phi(1)^T - phi(-1) phi(-1)^T (integration by parts on the
+    reference element), and the mass matrix is the Gauss weights."""
+    for P in (1, 2, 3):
+        d = _dg1d(2, P)
+        lhs = d.S + d.S.T
+        rhs = np.outer(d.phiR, d.phiR) - np.outer(d.phiL, d.phiL)
+        assert np.abs(lhs - rhs).max() < 1e-13
+        assert abs(d.w.sum() - 2.0) < 1e-14
+
+
+def test_rkdg_free_streaming_converges():
+    """Without collisions and with periodic ends every velocity point advects:
+    f(t, x, c) = g(x - c_x t).  The DG error drops at the expected rate."""
+    from oracle import rkdg
+    errs = []
+    for I in (4, 8, 16):
+        d = _dg1d(I, 2, N=4, L=2.0)
+        x = d.nodes_x()
+        cx = d.cv[0]
+        g = lambda y: 1.0 + 0.3 * np.sin(2 * np.pi * y)
+        F = g(x[:, :, None, None, None] - 0.0 * cx[None, None])
+        T, dt = 0.25, 0.2 / I / 2.0
+        steps = int(round(T / dt))
+        for _ in range(steps):
+            F = d.step(F, dt, rk=3)
+        exact = g(x[:, :, None, None, None] - cx[None, None] * steps * dt)
+        errs.append(np.abs(F - exact).max())
+    assert errs[0] > 6 * errs[1] > 36 * errs[2]
+    assert errs[2] < 1e-4
+
+
+def test_rkdg_diffuse_walls_conserve_mass_and_keep_wall_maxwellian():
+    from oracle import rkdg
+    N, L = 8, 5.0
+    wl = rkdg.Bc("wall", u=(0.0, -0.2, 0.0), T=0.9)
+    wr = rkdg.Bc("wall", u=(0.0, 0.2, 0.0), T=1.1)
+    d = _dg1d(3, 2, N=N, L=L, inv_kn=0.5, left=wl, right=wr,
+              faces=np.array([0.0, 0.2, 0.7, 1.0]))
+    x = d.nodes_x()
+    F = np.stack([[W.maxwellian(N, L, 1.0 + 0.2 * np.sin(3 * xx), np.array([0.1, 0.0, 0.0]), 1.0)
+                   for xx in row] for row in x])
+    m0 = d.total_mass(F)
+    F1 = d.step(F, 0.01, rk=2)
+    assert abs(d.total_mass(F1) - m0) <= 1e-13 * m0
+    # equal walls at rest with the matching Maxwellian everywhere: no transport
+    w0 = rkdg.Bc("wall", T=1.0)
+    d0 = _dg1d(3, 2, N=N, L=L, left=w0, right=rkdg.Bc("wall", T=1.0))
+    M = W.maxwellian(N, L, 1.0, np.zeros(3), 1.0)
+    F = np.broadcast_to(M, (3, 3) + M.shape).copy()
+    assert np.abs(d0.transport(F)).max() <= 1e-13 * np.abs(M).max()
+    assert abs(d0.wall_density("L", M) * np.pi ** 1.5 - 1.0) < 1e-13
+
+
+def test_rkdg_exact_and_collocated_collision_forms_agree_on_uniform_state():
+    """For a state constant inside each element both collision forms give Q of
+    that state at every node (the exact tensor sums to the mass matrix)."""
+    N, L = 8, 5.0
+    f = W.maxwellian_mixture(2, N, L, 21, noise=0.2)
+    F = np.stack([np.broadcast_to(f[i], (3,) + f[i].shape) for i in range(2)])
+    de = _dg1d(2, 2, N=N, L=L, inv_kn=1.0, coll="exact")
+    dc = _dg1d(2, 2, N=N, L=L, inv_kn=1.0, coll="collocation")
+    Ce, Cc = de.collision(F), dc.collision(F)
+    assert np.abs(Ce - Cc).max() <= 1e-12 * np.abs(Cc).max()
