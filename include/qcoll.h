@@ -274,6 +274,56 @@ qcoll_status qcoll_dg_collide_svd(qcoll_plan plan, int64_t n_elem, int32_t K, in
                                   const double *T1, const double *T2, const double *W, const double *F,
                                   double *C, int32_t conserve, void *ws, size_t ws_bytes, void *stream);
 
+/* 1-D RKDG driver (Section 3): DG in x on the K = P+1 Gauss-Legendre nodes of
+ * every element (diagonal mass matrix), the upwind flux of Section 3.2, the
+ * collision term of the weak form through the plan, SSP-RK2/RK3 of Section
+ * 3.5 and the boundary conditions of Section 3.6.  The walls are normal to x.
+ *   F, R: device FP64 [n_elem][K][N^3] nodal values (item order of qcoll_eval);
+ *   dF_m/dt = (c_x (S F)_m - face terms) / (J w_m) + inv_kn * C_m / (J w_m),
+ *   C_m = sum_{l1,l2} H_{m l1 l2} Q(F_l1, F_l2) with H exact (eigen form of the
+ *   triple tensor, coll_form 1) or from the K-point rule (C_m = J w_m Q(F_m),
+ *   coll_form 0).  The plan's precision applies to Q; the transport is FP64. */
+typedef struct qcoll_dg1d_s *qcoll_dg1d;
+
+typedef enum { QCOLL_BC_PERIODIC = 0, QCOLL_BC_WALL = 1, QCOLL_BC_INFLOW = 2 } qcoll_bc_kind;
+
+/* One end of the interval.  PERIODIC: both ends or neither.  WALL: fully
+ * diffuse at velocity u and temperature T; incoming velocities ((c - u).n < 0)
+ * see n_w exp(-|c - u|^2 / T) with n_w from zero net mass flux (discrete sums
+ * over the velocity grid).  INFLOW: incoming velocities (c.n < 0) see the
+ * Maxwellian n (pi T)^{-3/2} exp(-|c - u|^2 / T). */
+typedef struct {
+  int32_t kind;
+  double n;
+  double u[3];
+  double T;
+} qcoll_bc;
+
+typedef struct {
+  int32_t n_elem;        /* >= 1 */
+  const double *faces;   /* HOST [n_elem + 1], strictly increasing */
+  int32_t order;         /* P, 0..7 */
+  double inv_kn;         /* >= 0; 0 = free streaming (no collision term) */
+  int32_t coll_form;     /* 0 collocated, 1 exact triple tensor */
+  int32_t conserve;      /* project every Q evaluation (qcoll_conserve) */
+  qcoll_bc left, right;
+} qcoll_dg1d_params;
+
+/* The driver keeps the plan pointer (not owned: destroy the driver first) and
+ * small device tables.  EINVAL for bad parameters. */
+qcoll_status qcoll_dg1d_create(qcoll_plan plan, const qcoll_dg1d_params *p, qcoll_dg1d *out);
+qcoll_status qcoll_dg1d_destroy(qcoll_dg1d d);
+/* Node positions, HOST [n_elem][K]. */
+qcoll_status qcoll_dg1d_nodes(qcoll_dg1d d, double *host_x);
+/* Workspace for qcoll_dg1d_rhs (rk = 0) or qcoll_dg1d_step (rk = 1, 2, 3). */
+size_t qcoll_dg1d_workspace_bytes(qcoll_dg1d d, int32_t rk);
+/* R = L(F), the right-hand side of the semi-discrete system.  R must not
+ * overlap F. */
+qcoll_status qcoll_dg1d_rhs(qcoll_dg1d d, const double *F, double *R, void *ws, size_t ws_bytes, void *stream);
+/* One time step in place: rk = 1 forward Euler, 2 SSP-RK2, 3 SSP-RK3. */
+qcoll_status qcoll_dg1d_step(qcoll_dg1d d, double *F, double dt, int32_t rk, void *ws, size_t ws_bytes,
+                             void *stream);
+
 /* Synchronise the device, then report and clear the non-finite flag. */
 qcoll_status qcoll_poll(qcoll_plan plan);
 

@@ -30,6 +30,22 @@ class Params(ctypes.Structure):
                 ("svd_tol", ctypes.c_double), ("precision", ctypes.c_int32)]
 
 
+class Bc(ctypes.Structure):
+    """One end of a 1-D domain: kind 0 periodic, 1 diffuse wall (u, T), 2 inflow (n, u, T)."""
+    _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_double), ("u", ctypes.c_double * 3),
+                ("T", ctypes.c_double)]
+
+    def __init__(self, kind="periodic", n=1.0, u=(0.0, 0.0, 0.0), T=1.0):
+        code = {"periodic": 0, "wall": 1, "inflow": 2}[kind] if isinstance(kind, str) else int(kind)
+        super().__init__(code, float(n), (ctypes.c_double * 3)(*[float(x) for x in u]), float(T))
+
+
+class Dg1dParams(ctypes.Structure):
+    _fields_ = [("n_elem", ctypes.c_int32), ("faces", ctypes.POINTER(ctypes.c_double)),
+                ("order", ctypes.c_int32), ("inv_kn", ctypes.c_double), ("coll_form", ctypes.c_int32),
+                ("conserve", ctypes.c_int32), ("left", Bc), ("right", Bc)]
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("N_rho", ctypes.c_int32), ("M", ctypes.c_int32),
                 ("rank", ctypes.c_int32), ("precision", ctypes.c_int32),
@@ -82,6 +98,12 @@ def lib():
                                  i32),
             "qcoll_group_vjp": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                 ctypes.POINTER(vp), i32, vp, ctypes.c_size_t, vp, i32], i32),
+            "qcoll_dg1d_create": ([vp, ctypes.POINTER(Dg1dParams), ctypes.POINTER(vp)], i32),
+            "qcoll_dg1d_destroy": ([vp], i32),
+            "qcoll_dg1d_nodes": ([vp, ctypes.POINTER(ctypes.c_double)], i32),
+            "qcoll_dg1d_workspace_bytes": ([vp, i32], ctypes.c_size_t),
+            "qcoll_dg1d_rhs": ([vp, dp, dp, vp, ctypes.c_size_t, vp], i32),
+            "qcoll_dg1d_step": ([vp, dp, ctypes.c_double, i32, vp, ctypes.c_size_t, vp], i32),
             "qcoll_timing_enable": ([i32], i32),
             "qcoll_timing_reset": ([], i32),
             "qcoll_timing_select": ([ctypes.c_char_p], i32),
@@ -422,6 +444,75 @@ class Group:
                                      int(bool(through_conserve)), _ptr(ws), ws.numel(), _stream(stream),
                                      int(bool(use_graph))))
         return dfs
+
+
+class Dg1d:
+    """1-D RKDG driver over a plan (see include/qcoll.h): state F [n_elem][K][N][N][N]."""
+
+    def __init__(self, plan, faces, order, inv_kn, left=None, right=None, coll_form=0, conserve=True):
+        import numpy as np
+        self.plan = plan
+        self.faces = np.ascontiguousarray(faces, dtype=np.float64)
+        self.n_elem = len(self.faces) - 1
+        self.K = int(order) + 1
+        left = left if left is not None else Bc("periodic")
+        right = right if right is not None else Bc("periodic")
+        prm = Dg1dParams(self.n_elem, self.faces.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(order),
+                         float(inv_kn), int(coll_form), int(bool(conserve)), left, right)
+        h = ctypes.c_void_p()
+        _check(lib().qcoll_dg1d_create(plan._h, ctypes.byref(prm), ctypes.byref(h)))
+        self._h = h
+        self._ws = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            import torch
+            torch.cuda.synchronize()
+            lib().qcoll_dg1d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def nodes(self):
+        import numpy as np
+        x = np.zeros((self.n_elem, self.K))
+        _check(lib().qcoll_dg1d_nodes(self._h, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return x
+
+    def _workspace(self, rk):
+        import torch
+        need = int(lib().qcoll_dg1d_workspace_bytes(self._h, int(rk)))
+        ws = self._ws.get(rk)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.plan.device)
+            self._ws[rk] = ws
+        return ws
+
+    def _check_state(self, F):
+        import torch
+        N = self.plan.N
+        if tuple(F.shape) != (self.n_elem, self.K, N, N, N) or F.dtype != torch.float64 \
+                or not F.is_cuda or not F.is_contiguous():
+            raise ValueError(f"state must be a contiguous float64 CUDA tensor {(self.n_elem, self.K, N, N, N)}")
+
+    def rhs(self, F, R=None, stream=None):
+        import torch
+        self._check_state(F)
+        if R is None:
+            R = torch.empty_like(F)
+        ws = self._workspace(0)
+        _check(lib().qcoll_dg1d_rhs(self._h, _ptr(F), _ptr(R), _ptr(ws), ws.numel(), _stream(stream)))
+        return R
+
+    def step(self, F, dt, rk=3, stream=None):
+        self._check_state(F)
+        ws = self._workspace(rk)
+        _check(lib().qcoll_dg1d_step(self._h, _ptr(F), float(dt), int(rk), _ptr(ws), ws.numel(), _stream(stream)))
+        return F
 
 
 def collide(f, plan, omega=None, conserve=True):

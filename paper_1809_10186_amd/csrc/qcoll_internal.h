@@ -75,6 +75,7 @@ qcoll_status launch_vjp(const Plan &p, int64_t batch, const double *f, const dou
                         hipStream_t st);
 
 bool supported_N(int N);
+void gauss_legendre(int n, double a, double b, std::vector<double> &x, std::vector<double> &w);
 qcoll_status launch_dg_contract(const double *A, const double *X, double *Y, long E, int rows, int cols, long n3,
                                 hipStream_t st);
 bool fused_gain_supported(int N, int precision);

@@ -10,16 +10,12 @@
 
 namespace qcoll {
 
-namespace {
-
-constexpr double kPiD = 3.141592653589793238462643383279502884;
-
-// Gauss-Legendre nodes/weights on [a, b] by Newton iteration on P_n.
+// Gauss-Legendre nodes/weights on [a, b] (ascending) by Newton iteration on P_n.
 void gauss_legendre(int n, double a, double b, std::vector<double> &x, std::vector<double> &w) {
   x.assign(n, 0.0);
   w.assign(n, 0.0);
   for (int i = 0; i < n; ++i) {
-    double z = std::cos(kPiD * (i + 0.75) / (n + 0.5));
+    double z = std::cos(3.141592653589793238462643383279502884 * (i + 0.75) / (n + 0.5));
     double dp = 1.0;
     for (int it = 0; it < 100; ++it) {
       double p0 = 1.0, p1 = z;
@@ -49,6 +45,11 @@ void gauss_legendre(int n, double a, double b, std::vector<double> &x, std::vect
     w[n - 1 - i] = (b - a) / ((1.0 - z * z) * dp * dp);
   }
 }
+
+
+namespace {
+
+constexpr double kPiD = 3.141592653589793238462643383279502884;
 
 // built-in half-sphere rule: one vertex per antipodal pair of the icosahedron
 void icosahedral_half(std::vector<double> &s) {
