@@ -14,8 +14,9 @@ five-step pass with every kernel timed.
 
 Outside the headline, "secondary" times the rows that the step does not cover,
 each on its own synthetic workload: the DG weak-form term (MFMA contractions +
-batched Q), a VSS kernel (alpha = 1.5) on the same batch, the VJP, and the
-group launches (2D DG batch; uneven three-grid batch, forward and VJP).
+batched Q), a VSS kernel (alpha = 1.5) on the same batch, one SSP-RK2 step of
+the 1-D RKDG driver on the paper's Fourier heat-transfer setup, the VJP, and
+the group launches (2D DG batch; uneven three-grid batch, forward and VJP).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-acc] [--no-extras]
 """
@@ -224,6 +225,26 @@ def extras(qc, torch, W, reps=3):
                                       "evals_per_s": round(f.shape[0] / (ms * 1e-3), 1)}
         pl.close()
     del f, Qv
+
+    # RKDG driver (Section 3): Fourier heat transfer between walls at 263 K and
+    # 283 K (T0 = 273 K), Maxwell molecules, Kn 1.582 (Cercignani), 10 elements
+    # of order 2 refined towards the walls, [-5.09, 5.09]^3 with 24^3 points,
+    # M = 6: one SSP-RK2 step = 2 x (30 collision evaluations + transport)
+    h = 1.23 ** np.arange(5)
+    h = 0.5 * h / h.sum()
+    left = np.concatenate([[0.0], np.cumsum(h)])
+    faces = np.concatenate([left, 1.0 - left[::-1][1:]])
+    for prec, tag in ((qc.QCOLL_FP32, "fp32"), (qc.QCOLL_FP64, "fp64")):
+        pl = qc.Plan(24, 5.09, 12, sphere=None, omega=1.0, precision=prec)
+        dd = qc.Dg1d(pl, faces, 2, (np.pi / 2.0) / 1.582, qc.Bc("wall", T=263.0 / 273.0),
+                     qc.Bc("wall", T=283.0 / 273.0))
+        M0 = W.maxwellian(24, 5.09, 1.0, np.zeros(3), 1.0)
+        Fd = torch.from_numpy(np.broadcast_to(M0, (10, 3) + M0.shape).copy()).to("cuda")
+        ms = timeit(lambda: dd.step(Fd, 0.002, rk=2), n=10)
+        out[f"dg1d_fourier_rk2_{tag}"] = {"elements": 10, "order": 2, "grid": "24^3", "M": 6,
+                                          "ms_per_step": round(ms, 3), "q_evals_per_step": 60}
+        dd.close()
+        pl.close()
 
     # VJP (f and omega, through the conservation projection) on 256 items at 32^3
     w = W.WORKLOADS["adjoint_32"]

@@ -102,3 +102,46 @@ def test_dg1d_free_streaming_and_refusals():
         qc.Dg1d(plan, np.array([0.0, 1.0]), 2, 1.0, qc.Bc("wall"), qc.Bc("periodic"))
     with pytest.raises(qc.QcollError):
         gd.step(Fg, 0.01, rk=4)
+
+
+def fourier_faces(n_half=5, ratio=1.23):
+    """Element faces on [0, 1] refined geometrically towards both walls."""
+    h = ratio ** np.arange(n_half)
+    h = 0.5 * h / h.sum()
+    left = np.concatenate([[0.0], np.cumsum(h)])
+    return np.concatenate([left, 1.0 - left[::-1][1:]])
+
+
+def test_dg1d_fourier_heat_transfer_qualitative():
+    """Fourier heat transfer between walls at rest at 263 K and 283 K (T0 = 273 K),
+    Maxwell molecules, Kn (Cercignani) 1.582 -> 1/Kn_Bird = (pi/2)/1.582, 10
+    elements of order 2 refined towards the walls, [-5.09, 5.09]^3 with 16^3
+    points and M = 6 (a coarser velocity grid than the paper's 24^3).  Only
+    qualitative checks are possible without the DSMC data: near steady state the
+    temperature rises monotonically from the cold to the hot wall with jumps at
+    both walls, the density falls, the heat flux is negative and nearly uniform,
+    there is no net mass flow, and mass is conserved."""
+    Nv, Lv = 16, 5.09
+    Tl, Tr = 263.0 / 273.0, 283.0 / 273.0
+    faces = fourier_faces()
+    plan = qc.Plan(Nv, Lv, 8, sphere=None, omega=1.0, precision=qc.QCOLL_FP32)
+    inv_kn = (np.pi / 2.0) / 1.582
+    d = qc.Dg1d(plan, faces, 2, inv_kn, qc.Bc("wall", T=Tl), qc.Bc("wall", T=Tr))
+    x = d.nodes()
+    M0 = W.maxwellian(Nv, Lv, 1.0, np.zeros(3), 1.0)
+    F = gpu(np.broadcast_to(M0, x.shape + M0.shape).copy())
+    dc3 = (2 * Lv / Nv) ** 3
+    J = 0.5 * np.diff(faces)
+    wg = np.polynomial.legendre.leggauss(3)[1]
+    mass = lambda G: float(np.sum(J[:, None] * wg[None, :] * G.sum(dim=(2, 3, 4)).cpu().numpy() * dc3))
+    m0 = mass(F)
+    for _ in range(2500):
+        d.step(F, 0.002, rk=2)
+    mom = plan.moments(F.reshape(-1, Nv, Nv, Nv)).cpu().numpy().reshape(x.shape + (14,))
+    n, ux, T, qx = mom[..., 0].ravel(), mom[..., 1].ravel(), mom[..., 4].ravel(), mom[..., 11].ravel()
+    print("T", np.round(T, 4), "\nn", np.round(n, 4), "\nqx", np.round(qx, 5), flush=True)
+    assert abs(mass(F) - m0) <= 1e-10 * m0
+    assert np.all(np.diff(T) > 0) and Tl < T[0] and T[-1] < Tr
+    assert np.all(np.diff(n) < 0)
+    assert np.all(qx < 0) and (qx.max() - qx.min()) < 0.1 * abs(qx.mean())
+    assert np.abs(ux).max() < 1e-3
