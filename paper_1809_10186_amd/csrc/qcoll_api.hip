@@ -147,8 +147,8 @@ qcoll_status qcoll_plan_set_omega(qcoll_plan plan, double omega) {
 qcoll_status qcoll_plan_set_schedule(qcoll_plan plan, int32_t schedule) {
   if (!plan) return fail(QCOLL_EINVAL, "plan is NULL");
   if (schedule < 0 || schedule > 2) return fail(QCOLL_EINVAL, "schedule must be 0, 1 or 2");
-  if (schedule == 2 && (!qcoll::fused_gain_supported(plan->p.N, plan->p.precision) || plan->p.is_vss()))
-    return fail(QCOLL_ENOTSUP, "the fused gain kernel needs FP32, N <= 32 and a VHS kernel");
+  if (schedule == 2 && !qcoll::fused_gain_supported(plan->p.N, plan->p.precision))
+    return fail(QCOLL_ENOTSUP, "the fused gain kernel needs FP32 and N <= 32");
   plan->p.schedule = schedule;
   return QCOLL_OK;
 }

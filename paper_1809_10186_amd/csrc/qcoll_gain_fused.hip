@@ -96,17 +96,27 @@ __device__ __forceinline__ void lds_transpose_wave(float *lds, float (*v)[N], WA
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int N>
+// VSS = true: sigma-dependent kernel modes (VSS kernels).  Each term's
+// product t = Re(u)^2 - Im(u)^2 is transformed forward on chip (the same
+// transposes run backwards), weighted by alpha_pq(k) and accumulated as a
+// half spectrum (planes k1 <= N/2) in registers; the weights carry w_p w_q,
+// so the multiplier is not scaled by sqrt(w_q).  The epilogue stores that sum.
+template <int N, bool VSS>
 __global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<float> *__restrict__ H,
                                                                  const cplx<float> *__restrict__ phase,
                                                                  const float *__restrict__ wq,
                                                                  const float *__restrict__ alpha_eff,
+                                                                 const float *__restrict__ apq,
                                                                  cplx<float> *__restrict__ W, long nbp, int M,
                                                                  int Nr, float scale) {
   using G = FusedGeom<N>;
   constexpr int PPL = G::PPL, NL = G::NL;
+  constexpr int H1 = N / 2 + 1;
   constexpr long n2 = long(N) * N, n3 = n2 * N;
   constexpr int S1 = G::S1;
+  // accumulator: VHS A_p in the C layout (N real values per pencil); VSS the
+  // half spectrum in the A layout (re, im of planes k1 <= N/2)
+  constexpr int NACC = VSS ? 2 * H1 : N;
   extern __shared__ float lds[];
 
   // XCD-aware renumbering: block i runs on XCD i % 8; give each XCD a
@@ -128,22 +138,27 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<floa
     lo[decltype(u)::value] = t % N;
   });
 
-  float acc[PPL][N];
+  float acc[PPL][NACC];
   static_for<0, PPL>([&](auto u) {
-    static_for<0, N>([&](auto j) { acc[decltype(u)::value][decltype(j)::value] = 0.f; });
+    static_for<0, NACC>([&](auto j) { acc[decltype(u)::value][decltype(j)::value] = 0.f; });
   });
+  auto wa1 = [&](int u, int i) { return i * S1 + hi[u] * N + lo[u]; };
+  auto ra1 = [&](int u, int i) { return hi[u] * S1 + i * N + lo[u]; };
+  auto wa2 = [&](int u, int i) { return hi[u] * S1 + lo[u] * (N + 1) + i; };
+  auto ra2 = [&](int u, int i) { return hi[u] * S1 + i * (N + 1) + lo[u]; };
 
   const __amdgpu_buffer_rsrc_t hr = make_rsrc(H + b * n3, unsigned(n3 * sizeof(cplx<float>)));
   for (int q = 0; q < M; ++q) {
     const cplx<float> *ph = phase + size_t(p * M + q) * 3 * N;
     // the previous iteration's last reads (wave-local B -> C) must finish
-    // before this iteration's A -> B writes reach other waves' rows
-    if constexpr (G::WAVE_BC) __syncthreads();
+    // before this iteration's A -> B writes reach other waves' rows (the VSS
+    // iteration ends with a cross-wave transpose and its own barrier)
+    if constexpr (G::WAVE_BC && !VSS) __syncthreads();
     float zr[PPL][N], zi[PPL][N];
     // stage A: lane (k2, k3) = (hi, lo); c(k1) = Re(b1 b23) + Im(b1 b23),
     // scaled by sqrt(w_q) (the weights are positive), so that the product
     // below accumulates w_q (Re(u)^2 - Im(u)^2) with two FMAs per point
-    const float sc = scale * __builtin_sqrtf(wq[q]);
+    const float sc = VSS ? scale : scale * __builtin_sqrtf(wq[q]);
     static_for<0, PPL>([&](auto uu) {
       constexpr int u = decltype(uu)::value;
       const cplx<float> b2 = ph[N + hi[u]], b3 = ph[2 * N + lo[u]];
@@ -162,8 +177,6 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<floa
       fft_reg<N, +1, float>(zr[u], zi[u]);
     });
     // A -> B: element (j1, k2, k3) at j1*S1 + k2*N + k3
-    auto wa1 = [&](int u, int i) { return i * S1 + hi[u] * N + lo[u]; };
-    auto ra1 = [&](int u, int i) { return hi[u] * S1 + i * N + lo[u]; };
     if constexpr (G::WAVE_BC) {
       // A -> B crosses waves: barrier after the writes; the barrier after the
       // imaginary-part reads is not needed (B -> C below stays in own rows)
@@ -185,8 +198,6 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<floa
     }
     static_for<0, PPL>([&](auto u) { fft_reg<N, +1, float>(zr[decltype(u)::value], zi[decltype(u)::value]); });
     // B -> C: element (j1, j2, k3) at j1*S1 + k3*(N+1) + j2
-    auto wa2 = [&](int u, int i) { return hi[u] * S1 + lo[u] * (N + 1) + i; };
-    auto ra2 = [&](int u, int i) { return hi[u] * S1 + i * (N + 1) + lo[u]; };
     if constexpr (G::WAVE_BC) {
       lds_transpose_wave<N, PPL>(lds, zr, wa2, ra2);
       lds_transpose_wave<N, PPL>(lds, zi, wa2, ra2);
@@ -194,16 +205,64 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<floa
       lds_transpose<N, PPL>(lds, zr, wa2, ra2);
       lds_transpose<N, PPL>(lds, zi, wa2, ra2);
     }
+    if constexpr (!VSS) {
+      static_for<0, PPL>([&](auto uu) {
+        constexpr int u = decltype(uu)::value;
+        fft_reg<N, +1, float>(zr[u], zi[u]);
+        static_for<0, N>([&](auto j) {
+          constexpr int jj = decltype(j)::value;
+          acc[u][jj] += zr[u][jj] * zr[u][jj];
+          acc[u][jj] -= zi[u][jj] * zi[u][jj];
+        });
+      });
+    } else {
+      // t = t1 t2 of this term, forward along axis 3 (lane (j1, j2))
+      static_for<0, PPL>([&](auto uu) {
+        constexpr int u = decltype(uu)::value;
+        fft_reg<N, +1, float>(zr[u], zi[u]);
+        static_for<0, N>([&](auto j) {
+          constexpr int jj = decltype(j)::value;
+          const float t = zr[u][jj] * zr[u][jj] - zi[u][jj] * zi[u][jj];
+          zr[u][jj] = t;
+          zi[u][jj] = 0.f;
+        });
+        fft_reg<N, -1, float>(zr[u], zi[u]);
+      });
+      // C -> B (own rows), axis 2; B -> A (across waves), axis 1
+      if constexpr (G::WAVE_BC) {
+        lds_transpose_wave<N, PPL>(lds, zr, ra2, wa2);
+        lds_transpose_wave<N, PPL>(lds, zi, ra2, wa2);
+      } else {
+        lds_transpose<N, PPL>(lds, zr, ra2, wa2);
+        lds_transpose<N, PPL>(lds, zi, ra2, wa2);
+      }
+      static_for<0, PPL>([&](auto u) { fft_reg<N, -1, float>(zr[decltype(u)::value], zi[decltype(u)::value]); });
+      lds_transpose<N, PPL>(lds, zr, ra1, wa1);
+      lds_transpose<N, PPL>(lds, zi, ra1, wa1);
+      const float *a = apq + size_t(p * M + q) * (size_t(H1) * n2);
+      static_for<0, PPL>([&](auto uu) {
+        constexpr int u = decltype(uu)::value;
+        fft_reg<N, -1, float>(zr[u], zi[u]);
+        static_for<0, H1>([&](auto k) {
+          constexpr int kk = decltype(k)::value;
+          const float w = a[kk * n2 + lane + u * NL];
+          acc[u][2 * kk] += w * zr[u][kk];
+          acc[u][2 * kk + 1] += w * zi[u][kk];
+        });
+      });
+    }
+  }
+  if constexpr (VSS) {
+    cplx<float> *wout = W + bp * (long(H1) * n2);
     static_for<0, PPL>([&](auto uu) {
       constexpr int u = decltype(uu)::value;
-      fft_reg<N, +1, float>(zr[u], zi[u]);
-      static_for<0, N>([&](auto j) {
-        constexpr int jj = decltype(j)::value;
-        acc[u][jj] += zr[u][jj] * zr[u][jj];
-        acc[u][jj] -= zi[u][jj] * zi[u][jj];
+      static_for<0, H1>([&](auto k) {
+        constexpr int kk = decltype(k)::value;
+        wout[kk * n2 + lane + u * NL] = cplx<float>{acc[u][2 * kk], acc[u][2 * kk + 1]};
       });
     });
-  }
+    return;
+  } else {
   // Low-rank stage on chip: forward 3-D transform of the real A_p (the same
   // two transposes, run backwards), times the gain weights alpha_p(k) (or
   // their truncation, already / N^3), stored as the spectrum W[item][p].
@@ -219,10 +278,6 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<floa
       });
       fft_reg<N, -1, float>(zr[u], zi[u]);
     });
-    auto wa1 = [&](int u, int i) { return i * S1 + hi[u] * N + lo[u]; };
-    auto ra1 = [&](int u, int i) { return hi[u] * S1 + i * N + lo[u]; };
-    auto wa2 = [&](int u, int i) { return hi[u] * S1 + lo[u] * (N + 1) + i; };
-    auto ra2 = [&](int u, int i) { return hi[u] * S1 + i * (N + 1) + lo[u]; };
     lds_transpose<N, PPL>(lds, zr, ra2, wa2);
     lds_transpose<N, PPL>(lds, zi, ra2, wa2);
     static_for<0, PPL>([&](auto u) { fft_reg<N, -1, float>(zr[decltype(u)::value], zi[decltype(u)::value]); });
@@ -243,29 +298,36 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<floa
       });
     });
   }
+  }
 }
 
-template <int N>
+template <int N, bool VSS>
 static qcoll_status launch_fused(const Plan &p, const cplx<float> *H, cplx<float> *W, long nbp, hipStream_t st) {
   using G = FusedGeom<N>;
   // the LDS tile exceeds the default dynamic limit at N = 32; set per call
   // (cheap) so that every device the process uses gets the attribute
-  if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_gain_fused<N>),
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_gain_fused<N, VSS>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, int(G::lds_bytes)) != hipSuccess) {
     set_error("hipFuncSetAttribute failed for the fused gain kernel");
     return QCOLL_EDEVICE;
   }
   TimedLaunch tl("gain fused", st);
   const float scale = float(1.0 / double(long(N) * N * N));
-  hipLaunchKernelGGL(k_gain_fused<N>, dim3(unsigned(nbp)), dim3(G::NL), G::lds_bytes, st, H,
+  hipLaunchKernelGGL((k_gain_fused<N, VSS>), dim3(unsigned(nbp)), dim3(G::NL), G::lds_bytes, st, H,
                      reinterpret_cast<const cplx<float> *>(p.phase), reinterpret_cast<const float *>(p.wq),
-                     reinterpret_cast<const float *>(p.alpha_eff), W, nbp, p.M, p.N_rho, scale);
+                     reinterpret_cast<const float *>(p.alpha_eff), reinterpret_cast<const float *>(p.alpha_pq), W,
+                     nbp, p.M, p.N_rho, scale);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     set_error(std::string("gain fused: ") + hipGetErrorString(e));
     return QCOLL_EDEVICE;
   }
   return QCOLL_OK;
+}
+
+template <int N>
+static qcoll_status launch_fused_any(const Plan &p, const cplx<float> *H, cplx<float> *W, long nbp, hipStream_t st) {
+  return p.is_vss() ? launch_fused<N, true>(p, H, W, nbp, st) : launch_fused<N, false>(p, H, W, nbp, st);
 }
 
 bool fused_gain_supported(int N, int precision) {
@@ -276,11 +338,11 @@ qcoll_status launch_gain_fused(const Plan &p, const void *H, void *W, long nbp, 
   const auto *h = static_cast<const cplx<float> *>(H);
   auto *a = static_cast<cplx<float> *>(W);
   switch (p.N) {
-    case 8: return launch_fused<8>(p, h, a, nbp, st);
-    case 12: return launch_fused<12>(p, h, a, nbp, st);
-    case 16: return launch_fused<16>(p, h, a, nbp, st);
-    case 24: return launch_fused<24>(p, h, a, nbp, st);
-    case 32: return launch_fused<32>(p, h, a, nbp, st);
+    case 8: return launch_fused_any<8>(p, h, a, nbp, st);
+    case 12: return launch_fused_any<12>(p, h, a, nbp, st);
+    case 16: return launch_fused_any<16>(p, h, a, nbp, st);
+    case 24: return launch_fused_any<24>(p, h, a, nbp, st);
+    case 32: return launch_fused_any<32>(p, h, a, nbp, st);
     default: set_error("fused gain kernel: unsupported N"); return QCOLL_ENOTSUP;
   }
 }

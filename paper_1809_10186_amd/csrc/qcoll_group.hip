@@ -269,7 +269,7 @@ size_t qcoll_autotune_workspace_bytes(qcoll_plan plan, int64_t batch) {
   size_t mx = 0;
   for (int sch : {1, 2})
     for (int ck : tune_chunks(batch)) {
-      if (sch == 2 && (!qcoll::fused_gain_supported(p.N, p.precision) || p.is_vss())) continue;
+      if (sch == 2 && !qcoll::fused_gain_supported(p.N, p.precision)) continue;
       p.schedule = sch;
       p.chunk = ck;
       mx = std::max(mx, qcoll::make_layout(p, batch, 0).total);
@@ -322,7 +322,7 @@ qcoll_status qcoll_autotune(qcoll_plan plan, int64_t batch, const double *f, dou
   qcoll_status rc = QCOLL_OK;
   for (int sch : {2, 1})
     for (int ck : tune_chunks(batch)) {
-      if (sch == 2 && (!qcoll::fused_gain_supported(p.N, p.precision) || p.is_vss())) continue;
+      if (sch == 2 && !qcoll::fused_gain_supported(p.N, p.precision)) continue;
       p.schedule = sch;
       p.chunk = ck;
       const qcoll::Layout lay = qcoll::make_layout(p, batch, 0);

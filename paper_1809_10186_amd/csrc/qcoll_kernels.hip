@@ -496,7 +496,10 @@ struct Engine {
     const long nbp = nb * p.N_rho;
     const T scale = T(1.0 / double(n3));
     qcoll_status s;
-    for (long bp0 = 0; bp0 < nbp; bp0 += pc) {
+    // FP32 with N <= 32: the whole per-pair loop on chip (fused kernel, VSS mode)
+    const bool fused = std::is_same<T, float>::value && use_fused_gain(p);
+    if (fused && (s = launch_gain_fused(p, H, Wp, nbp, st))) return s;
+    for (long bp0 = 0; !fused && bp0 < nbp; bp0 += pc) {
       const long cnt = (nbp - bp0 < pc) ? (nbp - bp0) : pc;
       SrcShift<T, N> src{H, reinterpret_cast<const C<T> *>(p.phase), bp0, p.M, p.N_rho, scale};
       if ((s = slab<SrcShift<T, N>, DstCplx<T, N>, +1>(src, DstCplx<T, N>{Y}, cnt * p.M * N, st, "gain slab")))
@@ -754,7 +757,7 @@ __global__ __launch_bounds__(256) void k_moments(const double *F, double *out, i
 
 // ----------------------------------------------------------------------------
 bool use_fused_gain(const Plan &p) {
-  return p.schedule != 1 && !p.is_vss() && fused_gain_supported(p.N, p.precision);
+  return p.schedule != 1 && fused_gain_supported(p.N, p.precision);
 }
 
 Layout make_layout(const Plan &p, int64_t batch, int op) {

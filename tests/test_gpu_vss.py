@@ -102,8 +102,26 @@ def test_vss_refused_operations():
     with pytest.raises(qc.QcollError) as e:
         plan.eval_bilinear(f, f)
     assert e.value.code == 2
-    with pytest.raises(qc.QcollError) as e:
-        plan.set_schedule(2)
-    assert e.value.code == 2
+    # the fused schedule has a VSS mode (FP32, N <= 32): requesting it is valid
+    plan.set_schedule(2)
     # the plan still evaluates after the refusals
     assert torch.isfinite(plan.eval(f)).all()
+
+
+@pytest.mark.parametrize("N", [24, 32])
+def test_vss_fused_schedule_matches_two_pass(N):
+    """FP32 VSS plans run the gain loop on chip (fused kernel, VSS mode) by
+    default; the two-pass schedule computes the same operator.  Both against
+    the FP64 VSS plan on the 1D DG batch's grid."""
+    L, Nr, M = 6.0, 8, 12
+    sph = W.sphere_rule(M)
+    f = gpu(W.maxwellian_mixture(3, N, L, 91))
+    p64 = qc.Plan(N, L, Nr, sphere=sph, omega=0.81, precision=qc.QCOLL_FP64, alpha=1.5)
+    ref = p64.eval(f).cpu().numpy()
+    fused = qc.Plan(N, L, Nr, sphere=sph, omega=0.81, precision=qc.QCOLL_FP32, alpha=1.5)
+    two = qc.Plan(N, L, Nr, sphere=sph, omega=0.81, precision=qc.QCOLL_FP32, alpha=1.5)
+    two.set_schedule(1)
+    e1 = rel(fused.eval(f).cpu().numpy(), ref)
+    e2 = rel(two.eval(f).cpu().numpy(), ref)
+    print(f"VSS N={N}: fused {e1:.3e} two-pass {e2:.3e}", flush=True)
+    assert e1 <= 2e-5 and e2 <= 2e-5
