@@ -86,15 +86,43 @@ struct OpGainAcc2 {
 };
 
 // low-rank mixing: B[b][s] = sum_p U[s][p] A[b][p]
-template <typename T>
-__global__ void k_mix(const T *A, const T *U, T *B, long nitems, int S, int Nr, long n3) {
+template <typename T, int NRM>
+__global__ __launch_bounds__(256) void k_mix(const T *A, const T *U, T *B, long nitems, int S, int Nr, long n3) {
+  // one point per lane: its Nr (<= NRM) node values are loaded once into
+  // registers; U (S x Nr, S <= Nr) is staged per block in LDS, zero-padded to
+  // NRM columns, and read at one address per wave (broadcast)
+  __shared__ T us[NRM * NRM];
+  for (int t = threadIdx.x; t < S * NRM; t += blockDim.x) {
+    const int s = t / NRM, q = t % NRM;
+    us[t] = (q < Nr) ? U[s * Nr + q] : T(0);
+  }
+  __syncthreads();
   const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= nitems * n3) return;
   const long b = i / n3, j = i % n3;
+  const T *a0 = A + b * Nr * n3 + j;
+  T a[NRM];
+#pragma unroll
+  for (int q = 0; q < NRM; ++q) a[q] = (q < Nr) ? a0[q * n3] : T(0);
+  T *b0 = B + b * S * n3 + j;
   for (int s = 0; s < S; ++s) {
     T acc = T(0);
-    for (int p = 0; p < Nr; ++p) acc += U[s * Nr + p] * A[(b * Nr + p) * n3 + j];
-    B[(b * S + s) * n3 + j] = acc;
+#pragma unroll
+    for (int q = 0; q < NRM; ++q) acc += us[s * NRM + q] * a[q];
+    b0[s * n3] = acc;
+  }
+}
+
+template <typename T>
+static void launch_mix(const T *A, const T *U, T *B, long nitems, int S, int Nr, long n3, hipStream_t st) {
+  const dim3 g(nblk(nitems * n3, 256)), blk(256);
+  switch (mix_width(Nr)) {
+    case 8: hipLaunchKernelGGL((k_mix<T, 8>), g, blk, 0, st, A, U, B, nitems, S, Nr, n3); break;
+    case 16: hipLaunchKernelGGL((k_mix<T, 16>), g, blk, 0, st, A, U, B, nitems, S, Nr, n3); break;
+    case 24: hipLaunchKernelGGL((k_mix<T, 24>), g, blk, 0, st, A, U, B, nitems, S, Nr, n3); break;
+    case 32: hipLaunchKernelGGL((k_mix<T, 32>), g, blk, 0, st, A, U, B, nitems, S, Nr, n3); break;
+    case 48: hipLaunchKernelGGL((k_mix<T, 48>), g, blk, 0, st, A, U, B, nitems, S, Nr, n3); break;
+    default: hipLaunchKernelGGL((k_mix<T, 64>), g, blk, 0, st, A, U, B, nitems, S, Nr, n3); break;
   }
 }
 
@@ -607,8 +635,7 @@ struct Engine {
       const T *Bsrc = A;
       if (!p.mix_identity) {
         TimedLaunch tl("mix", st);
-        hipLaunchKernelGGL(k_mix<T>, dim3(nblk(nb * n3, 256)), dim3(256), 0, st, A,
-                           reinterpret_cast<const T *>(p.umix_d), B, nb, S, p.N_rho, n3);
+        launch_mix<T>(A, reinterpret_cast<const T *>(p.umix_d), B, nb, S, p.N_rho, n3, st);
         QC_LAUNCH_CHECK("mix");
         Bsrc = B;
       }

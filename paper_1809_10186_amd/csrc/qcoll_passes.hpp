@@ -174,6 +174,10 @@ __global__ void k_cast(const C<double> *in, C<T> *out, long n) {
 
 inline unsigned nblk(long n, int b) { return unsigned((n + b - 1) / b); }
 
+// register width of the low-rank mixing kernels for n (<= 64) radial nodes:
+// the next of 8, 16, 24, 32, 48, 64
+inline int mix_width(int n) { return n <= 32 ? ((n + 7) / 8) * 8 : (n <= 48 ? 48 : 64); }
+
 #define QC_LAUNCH_CHECK(what)                                           \
   do {                                                                  \
     hipError_t e_ = hipGetLastError();                                  \

@@ -51,20 +51,50 @@ struct SrcVPair {
 };
 
 // h_p = sum_s U[s][p] R_s, R_s = Re/Im of the packed pair buffer
-template <typename T>
-__global__ void k_unpack_mix(const C<T> *R, const T *U, T *Hp, long nitems, int S, int Nr, int npair, long n3) {
+template <typename T, int NRM>
+__global__ __launch_bounds__(256) void k_unpack_mix(const C<T> *R, const T *U, T *Hp, long nitems, int S, int Nr,
+                                                    int npair, long n3) {
+  // the S (<= Nr <= NRM) packed values of the point are loaded once into
+  // registers; U (S x Nr) is staged per block in LDS, transposed and
+  // zero-padded to NRM rows, and read at one address per wave (broadcast)
+  __shared__ T ut[NRM * NRM];
+  for (int t = threadIdx.x; t < Nr * NRM; t += blockDim.x) {
+    const int q = t / NRM, s = t % NRM;
+    ut[t] = (s < S) ? U[s * Nr + q] : T(0);
+  }
+  __syncthreads();
   const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= nitems * n3) return;
   const long b = i / n3, j = i % n3;
-  T rv[64];
-  for (int s = 0; s < S; ++s) {
-    const C<T> x = R[(b * npair + s / 2) * n3 + j];
-    rv[s] = (s % 2 == 0) ? x.re : x.im;
+  const C<T> *r0 = R + b * npair * n3 + j;
+  T rv[NRM];
+#pragma unroll
+  for (int k = 0; k < NRM / 2; ++k) {
+    C<T> x{T(0), T(0)};
+    if (2 * k < S) x = r0[k * n3];
+    rv[2 * k] = x.re;
+    rv[2 * k + 1] = x.im;
   }
-  for (int p = 0; p < Nr; ++p) {
+  T *h0 = Hp + b * Nr * n3 + j;
+  for (int q = 0; q < Nr; ++q) {
     T acc = T(0);
-    for (int s = 0; s < S; ++s) acc += U[s * Nr + p] * rv[s];
-    Hp[(b * Nr + p) * n3 + j] = acc;
+#pragma unroll
+    for (int s = 0; s < NRM; ++s) acc += ut[q * NRM + s] * rv[s];
+    h0[q * n3] = acc;
+  }
+}
+
+template <typename T>
+static void launch_unpack_mix(const C<T> *R, const T *U, T *Hp, long nitems, int S, int Nr, int npair, long n3,
+                              hipStream_t st) {
+  const dim3 g(nblk(nitems * n3, 256)), blk(256);
+  switch (mix_width(Nr)) {
+    case 8: hipLaunchKernelGGL((k_unpack_mix<T, 8>), g, blk, 0, st, R, U, Hp, nitems, S, Nr, npair, n3); break;
+    case 16: hipLaunchKernelGGL((k_unpack_mix<T, 16>), g, blk, 0, st, R, U, Hp, nitems, S, Nr, npair, n3); break;
+    case 24: hipLaunchKernelGGL((k_unpack_mix<T, 24>), g, blk, 0, st, R, U, Hp, nitems, S, Nr, npair, n3); break;
+    case 32: hipLaunchKernelGGL((k_unpack_mix<T, 32>), g, blk, 0, st, R, U, Hp, nitems, S, Nr, npair, n3); break;
+    case 48: hipLaunchKernelGGL((k_unpack_mix<T, 48>), g, blk, 0, st, R, U, Hp, nitems, S, Nr, npair, n3); break;
+    default: hipLaunchKernelGGL((k_unpack_mix<T, 64>), g, blk, 0, st, R, U, Hp, nitems, S, Nr, npair, n3); break;
   }
 }
 
@@ -358,8 +388,7 @@ struct Vjp {
       if ((s = P::pencil(OpPencilInPlace<T, N, +1>{R}, nb * np * N * N, st, "vjp h pencil"))) return s;
       {
         TimedLaunch tl("vjp unpack", st);
-        hipLaunchKernelGGL(k_unpack_mix<T>, dim3(nblk(nb * n3, 256)), dim3(256), 0, st, R,
-                           reinterpret_cast<const T *>(p.umix_d), Hp, nb, S, Nr, np, n3);
+        launch_unpack_mix<T>(R, reinterpret_cast<const T *>(p.umix_d), Hp, nb, S, Nr, np, n3, st);
         QC_LAUNCH_CHECK("vjp unpack");
       }
       if (domega) {
