@@ -50,11 +50,14 @@ struct Plan {
 };
 
 // workspace layout for one call; sizes in bytes, offsets 256-aligned
+// blocks per item of the VJP conservation projection (one partial-moment row each)
+constexpr int kProjSeg = 16;
+
 struct Layout {
   long bc = 0;          // items per chunk
   long pc = 0;          // eval: (item, radial node) pairs per hot-loop launch; vjp: items per sub-chunk
   size_t off_h = 0, off_h64 = 0, off_a = 0, off_b = 0, off_w = 0, off_t = 0, off_l = 0, off_y = 0;
-  size_t off_g = 0, off_z = 0, off_hp = 0, off_d = 0;  // vjp extras
+  size_t off_g = 0, off_z = 0, off_hp = 0, off_d = 0, off_pm = 0;  // vjp extras
   size_t off_hg = 0, off_h64g = 0, off_yg = 0;          // bilinear extras
   size_t total = 0;
 };

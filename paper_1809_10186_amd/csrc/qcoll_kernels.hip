@@ -815,6 +815,7 @@ Layout make_layout(const Plan &p, int64_t batch, int op) {
     l.off_l = o; o += al(c64);
     l.off_a = o; o += al(size_t(l.bc) * n3 * sizeof(double));
     l.off_d = o; o += al(size_t(l.bc) * p.N_rho * sizeof(double));
+    l.off_pm = o; o += al(size_t(l.bc) * kProjSeg * 5 * sizeof(double));
     l.total = o;
     return l;
   }

@@ -288,18 +288,30 @@ __global__ __launch_bounds__(256) void k_domega(const C<double> *H, const C<doub
   if (threadIdx.x == 0) domega[b] = tot;
 }
 
-// out = P in (conservation projection, out of place), one workgroup per item
-__global__ __launch_bounds__(256) void k_project(const double *in, double *out, const double *ginv, int N,
-                                                 double L) {
-  const long n3 = long(N) * N * N;
-  const long b = blockIdx.x;
-  const double *x = in + b * n3;
-  double *y = out + b * n3;
+// Conservation projection of the cotangent, g -> g - sum_a lam_a phi_a with
+// lam = G^-1 <phi, g> (phi = 1, c, |c|^2 on the grid).  An item is split into
+// kProjSeg segments of one block each, so that a chunk of a few tens of items
+// still fills the GPU: the first kernel writes the segment's five moment sums,
+// the second adds the segments' sums in a fixed order and applies the update.
+
+__device__ __forceinline__ void grid_coord(int j, int N, double L, double &c1, double &c2, double &c3) {
   const double dc = 2.0 * L / N;
+  const int i1 = j / (N * N), i2 = (j / N) % N, i3 = j % N;
+  c1 = -L + (i1 + 0.5) * dc;
+  c2 = -L + (i2 + 0.5) * dc;
+  c3 = -L + (i3 + 0.5) * dc;
+}
+
+__global__ __launch_bounds__(256) void k_project_moments(const double *in, double *part, int N, double L) {
+  const int n3 = N * N * N, seg = (n3 + kProjSeg - 1) / kProjSeg;
+  const long b = blockIdx.x / kProjSeg;
+  const int g = blockIdx.x % kProjSeg;
+  const int j0 = g * seg, j1 = (j0 + seg < n3) ? j0 + seg : n3;
+  const double *x = in + b * n3;
   double s[5] = {0, 0, 0, 0, 0};
-  for (long j = threadIdx.x; j < n3; j += blockDim.x) {
-    const int i1 = int(j / (N * N)), i2 = int((j / N) % N), i3 = int(j % N);
-    const double c1 = -L + (i1 + 0.5) * dc, c2 = -L + (i2 + 0.5) * dc, c3 = -L + (i3 + 0.5) * dc;
+  for (int j = j0 + int(threadIdx.x); j < j1; j += blockDim.x) {
+    double c1, c2, c3;
+    grid_coord(j, N, L, c1, c2, c3);
     const double v = x[j];
     s[0] += v;
     s[1] += v * c1;
@@ -315,15 +327,33 @@ __global__ __launch_bounds__(256) void k_project(const double *in, double *out, 
       for (int k = 0; k < 5; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
     __syncthreads();
   }
+  if (threadIdx.x < 5) part[blockIdx.x * 5 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_project_apply(const double *in, double *out, const double *part,
+                                                       const double *ginv, int N, double L) {
+  const int n3 = N * N * N, seg = (n3 + kProjSeg - 1) / kProjSeg;
+  const long b = blockIdx.x / kProjSeg;
+  const int g = blockIdx.x % kProjSeg;
+  const int j0 = g * seg, j1 = (j0 + seg < n3) ? j0 + seg : n3;
+  __shared__ double mom[5];
+  if (threadIdx.x < 5) {
+    double m = 0;
+    for (int h = 0; h < kProjSeg; ++h) m += part[(b * kProjSeg + h) * 5 + threadIdx.x];
+    mom[threadIdx.x] = m;
+  }
+  __syncthreads();
   double lam[5];
   for (int a = 0; a < 5; ++a) {
     double acc = 0;
-    for (int c = 0; c < 5; ++c) acc += ginv[a * 5 + c] * red[c][0];
+    for (int c = 0; c < 5; ++c) acc += ginv[a * 5 + c] * mom[c];
     lam[a] = acc;
   }
-  for (long j = threadIdx.x; j < n3; j += blockDim.x) {
-    const int i1 = int(j / (N * N)), i2 = int((j / N) % N), i3 = int(j % N);
-    const double c1 = -L + (i1 + 0.5) * dc, c2 = -L + (i2 + 0.5) * dc, c3 = -L + (i3 + 0.5) * dc;
+  const double *x = in + b * n3;
+  double *y = out + b * n3;
+  for (int j = j0 + int(threadIdx.x); j < j1; j += blockDim.x) {
+    double c1, c2, c3;
+    grid_coord(j, N, L, c1, c2, c3);
     y[j] = x[j] - (lam[0] + lam[1] * c1 + lam[2] * c2 + lam[3] * c3 + lam[4] * (c1 * c1 + c2 * c2 + c3 * c3));
   }
 }
@@ -355,6 +385,7 @@ struct Vjp {
     C<double> *Lm = reinterpret_cast<C<double> *>(w + lay.off_l);
     double *gproj = reinterpret_cast<double *>(w + lay.off_a);
     double *dwg = reinterpret_cast<double *>(w + lay.off_d);
+    double *pm = reinterpret_cast<double *>(w + lay.off_pm);
     const int S = p.nv, np = p.npair(), Nr = p.N_rho, M = p.M;
     qcoll_status s;
     for (long b0 = 0; b0 < batch; b0 += lay.bc) {
@@ -363,7 +394,9 @@ struct Vjp {
       const double *gb = g_in + b0 * n3;
       if (through) {
         TimedLaunch tl("vjp project", st);
-        hipLaunchKernelGGL(k_project, dim3(unsigned(nb)), dim3(256), 0, st, gb, gproj, p.ginv, N, p.L);
+        hipLaunchKernelGGL(k_project_moments, dim3(unsigned(nb * kProjSeg)), dim3(256), 0, st, gb, pm, N, p.L);
+        hipLaunchKernelGGL(k_project_apply, dim3(unsigned(nb * kProjSeg)), dim3(256), 0, st, gb, gproj, pm, p.ginv,
+                           N, p.L);
         QC_LAUNCH_CHECK("vjp project");
         gb = gproj;
       }
