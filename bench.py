@@ -77,8 +77,10 @@ def model_flops_per_term(N):
     return 5.0 * n3 * math.log2(n3) + 10.0 * n3
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+def measured_traffic(kernel, items_per_launch):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, scaled
+    from the items per launch the counters were taken at to this run's (both the
+    spectra read and the per-node spectra written grow linearly with it), or None
     if the kernel source changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -88,7 +90,9 @@ def measured_traffic(kernel):
     ent = d.get(kernel)
     if not ent or ent.get("source_sha256") != source_digest(ent.get("sources", [])):
         return None
-    return ent.get("bytes_per_launch")
+    b = ent.get("bytes_per_launch")
+    n0 = ent.get("items_per_launch")
+    return b if b is None or not n0 else b * items_per_launch / n0
 
 
 def source_digest(files):
@@ -108,7 +112,7 @@ def roofline(name, tot_ms, launches, steps, B, N, Nr, M):
     n3 = N ** 3
     avg_ms = tot_ms / launches
     base = {"kernel": name, "avg_launch_ms": round(avg_ms, 4), "launches": launches,
-            "traffic": measured_traffic(name)}
+            "traffic": measured_traffic(name, B * steps / launches)}
     if name == "gain fused":
         # ALU bound: model flops of every (item, p, q) term of the timed region
         flops = B * Nr * M * steps * model_flops_per_term(N)
