@@ -138,7 +138,10 @@ qcoll_status qcoll_plan_set_omega(qcoll_plan plan, double omega);
 /* Hot-loop schedule: 0 = automatic (fused single-pass kernel where it is
  * available: FP32 with N <= 32; otherwise two passes over HBM), 1 = force the
  * two-pass schedule, 2 = require the fused kernel (ENOTSUP where it is not
- * available).  Results agree to rounding; workspace sizes depend on it. */
+ * available).  Results agree to rounding; workspace sizes depend on it.
+ * The schedule requested here also selects the gain adjoint of qcoll_vjp
+ * (fused unless 1 was requested; the autotuner's choice of the forward
+ * schedule does not change it). */
 qcoll_status qcoll_plan_set_schedule(qcoll_plan plan, int32_t schedule);
 
 /* Workspace needed by op 0 (qcoll_eval), 1 (qcoll_vjp) or 2 (qcoll_eval_bilinear)

@@ -150,6 +150,7 @@ qcoll_status qcoll_plan_set_schedule(qcoll_plan plan, int32_t schedule) {
   if (schedule == 2 && !qcoll::fused_gain_supported(plan->p.N, plan->p.precision))
     return fail(QCOLL_ENOTSUP, "the fused gain kernel needs FP32 and N <= 32");
   plan->p.schedule = schedule;
+  plan->p.schedule_user = schedule;
   return QCOLL_OK;
 }
 

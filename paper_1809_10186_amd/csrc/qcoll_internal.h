@@ -22,6 +22,7 @@ struct Plan {
   bool truncated = false;        // SVD truncation requested (any svd_rank >= 0)
   bool mix_identity = true;      // B_s = A_s (no SVD rotation)
   int schedule = 0;              // hot-loop schedule: 0 auto, 1 two-pass, 2 fused
+  int schedule_user = 0;         // the schedule last requested through the API (the autotuner leaves it)
   int chunk = 0;                 // items per eval chunk (0: default 64)
   double sigma_max = 0, sigma_min_kept = 0;
 
@@ -50,14 +51,16 @@ struct Plan {
 };
 
 // workspace layout for one call; sizes in bytes, offsets 256-aligned
-// blocks per item of the VJP conservation projection (one partial-moment row each)
+// blocks per item of the VJP conservation projection (one partial-moment row
+// each) and of the loss part of its omega gradient (one row of N_rho sums each)
 constexpr int kProjSeg = 16;
+constexpr int kDomSeg = 16;
 
 struct Layout {
   long bc = 0;          // items per chunk
   long pc = 0;          // eval: (item, radial node) pairs per hot-loop launch; vjp: items per sub-chunk
   size_t off_h = 0, off_h64 = 0, off_a = 0, off_b = 0, off_w = 0, off_t = 0, off_l = 0, off_y = 0;
-  size_t off_g = 0, off_z = 0, off_hp = 0, off_d = 0, off_pm = 0;  // vjp extras
+  size_t off_g = 0, off_z = 0, off_hp = 0, off_d = 0, off_pm = 0, off_dp = 0;  // vjp extras
   size_t off_hg = 0, off_h64g = 0, off_yg = 0;          // bilinear extras
   size_t total = 0;
 };
@@ -84,6 +87,12 @@ qcoll_status launch_dg_contract(const double *A, const double *X, double *Y, lon
 bool fused_gain_supported(int N, int precision);
 bool use_fused_gain(const Plan &p);
 qcoll_status launch_gain_fused(const Plan &p, const void *H, void *W, long nbp, hipStream_t st);
+// sum over the N_rho per-node spectra of each item (FP32 complex, float4 units)
+void launch_sum_nodes(const void *W, void *out, long nitems, int Nr, long n_in, long n_out, hipStream_t st);
+// fused gain adjoint of the VJP (FP32, N <= 32, VHS kernels)
+bool use_fused_adjoint(const Plan &p);
+qcoll_status launch_adjoint_fused(const Plan &p, const void *H, const float *Hp, void *Zh, double *dwg, long nbp,
+                                  hipStream_t st);
 
 // kernel timing (hipEvents on the launch stream) for roofline accounting
 bool timing_on();

@@ -203,6 +203,11 @@ __global__ __launch_bounds__(256) void k_sum_nodes(const float4 *__restrict__ W,
   out[b * n_out + o] = acc;
 }
 
+void launch_sum_nodes(const void *W, void *out, long nitems, int Nr, long n_in, long n_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_nodes, dim3(nblk(nitems * n_in, 256)), dim3(256), 0, st,
+                     static_cast<const float4 *>(W), static_cast<float4 *>(out), nitems, Nr, n_in, n_out);
+}
+
 // the same node sum for FP64 spectra: one complex value (16 bytes) per lane
 __global__ __launch_bounds__(256) void k_sum_nodes64(const double2 *__restrict__ W, double2 *__restrict__ out,
                                                      long nitems, int Nr, long n_in, long n_out) {
@@ -222,25 +227,7 @@ __global__ __launch_bounds__(256) void k_sum_nodes64(const double2 *__restrict__
 
 // Half spectra.  The gain and loss spectra are Hermitian (their inverse
 // transforms are real), so the fused schedule keeps only the planes
-// k1 <= N/2 of each item.  Slab g of such a pass is plane g % (N/2 + 1) of
-// item g / (N/2 + 1); its place in the full [item][k1] numbering:
-template <int N>
-__device__ __forceinline__ long half_slab(long g) {
-  constexpr int H1 = N / 2 + 1;
-  return (g / H1) * N + g % H1;
-}
-
-template <typename T, int N>
-struct SrcCplxHalf {
-  const C<T> *in;
-  __device__ C<T> operator()(long g, int r, int c) const { return in[(half_slab<N>(g) * N + r) * N + c]; }
-};
-
-template <typename T, int N>
-struct DstCplxHalf {
-  C<T> *out;
-  __device__ void operator()(long g, int r, int c, C<T> v) const { out[(half_slab<N>(g) * N + r) * N + c] = v; }
-};
+// k1 <= N/2 of each item (half_slab, SrcCplxHalf, DstCplxHalf).
 
 // loss, slab pass (FP64): Lambda * H64, slab g = item*N + k1
 template <int N>
@@ -810,12 +797,17 @@ Layout make_layout(const Plan &p, int64_t batch, int op) {
     l.off_w = o; o += al(cT);
     l.off_b = o; o += al(size_t(l.bc) * p.npair() * n3 * 2 * es);
     l.off_hp = o; o += al(size_t(l.bc) * p.N_rho * n3 * es);
-    l.off_y = o; o += al(size_t(l.pc) * per_item_y);
+    // the fused adjoint keeps its per-term volumes on chip: Y holds only the
+    // pairs' half spectra
+    const size_t y_bytes = use_fused_adjoint(p) ? size_t(l.bc) * p.N_rho * (p.N / 2 + 1) * p.N * p.N * 2 * es
+                                                : size_t(l.pc) * per_item_y;
+    l.off_y = o; o += al(y_bytes);
     l.off_t = o; o += al(cT);
     l.off_l = o; o += al(c64);
     l.off_a = o; o += al(size_t(l.bc) * n3 * sizeof(double));
     l.off_d = o; o += al(size_t(l.bc) * p.N_rho * sizeof(double));
     l.off_pm = o; o += al(size_t(l.bc) * kProjSeg * 5 * sizeof(double));
+    l.off_dp = o; o += al(size_t(l.bc) * kDomSeg * p.N_rho * sizeof(double));
     l.total = o;
     return l;
   }

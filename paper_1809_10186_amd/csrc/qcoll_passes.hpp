@@ -219,4 +219,25 @@ struct Passes {
 
 };
 
+// Half spectra: slab g of a pass over the planes k1 <= N/2 of every item is
+// plane g % (N/2 + 1) of item g / (N/2 + 1), kept in the full [item][k1][k2][k3]
+// layout (the planes k1 > N/2 follow by Hermitian symmetry).
+template <int N>
+__device__ __forceinline__ long half_slab(long g) {
+  constexpr int H1 = N / 2 + 1;
+  return (g / H1) * N + g % H1;
+}
+
+template <typename T, int N>
+struct SrcCplxHalf {
+  const C<T> *in;
+  __device__ C<T> operator()(long g, int r, int c) const { return in[(half_slab<N>(g) * N + r) * N + c]; }
+};
+
+template <typename T, int N>
+struct DstCplxHalf {
+  C<T> *out;
+  __device__ void operator()(long g, int r, int c, C<T> v) const { out[(half_slab<N>(g) * N + r) * N + c] = v; }
+};
+
 }  // namespace qcoll

@@ -17,6 +17,8 @@
 // axes forward and accumulates c_s * (.) for every (p, q) of the item.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "qcoll_passes.hpp"
 
 namespace qcoll {
@@ -262,30 +264,126 @@ struct OpVjpAssemble {
   }
 };
 
-// loss part of the omega gradient and the final combination, one workgroup per item:
-// domega[b] = sum_p dlog_p ( dwg[b][p] - (1/N^3) sum_k Re(conj(FG) H) Lam_p(k) )
-__global__ __launch_bounds__(256) void k_domega(const C<double> *H, const C<double> *FG, const double *lam_p,
-                                                const double *dlog, const double *dwg, double *domega, int Nr,
-                                                long n3) {
-  const long b = blockIdx.x;
-  __shared__ double red[256];
-  double tot = 0.0;
-  for (int p = 0; p < Nr; ++p) {
-    double s = 0.0;
-    for (long k = threadIdx.x; k < n3; k += blockDim.x) {
-      const C<double> h = H[b * n3 + k], x = FG[b * n3 + k];
-      s += (x.re * h.re + x.im * h.im) * lam_p[p * n3 + k];
+// final pencil pass of the fused adjoint: the gain part arrives as the planes
+// k1 <= N/2 of the Hermitian spectrum Zh (already transformed along axes 2 and
+// 3; the planes k1 > N/2 are the conjugates of planes N - k1 at the same
+// (j2, j3)), with 2 Re ifft3[Z] = ifft3[Zh]:
+// df = ifft(Zh)/N^3 - g Re(L) - Im(L)
+template <typename T, int N>
+struct OpVjpAssembleHalf {
+  const C<T> *Z;
+  const C<double> *Lm;
+  const double *g;
+  double *df;
+  __device__ void operator()(long b, int r) const {
+    constexpr long n2 = long(N) * N, n3 = n2 * N;
+    constexpr int H1 = N / 2 + 1;
+    double out[N];
+    {
+      T zr[N], zi[N];
+      const C<T> *x = Z + b * n3 + r;
+      static_for<0, H1>([&](auto k) {
+        const C<T> v = x[decltype(k)::value * n2];
+        zr[decltype(k)::value] = v.re;
+        zi[decltype(k)::value] = v.im;
+      });
+      static_for<H1, N>([&](auto k) {
+        zr[decltype(k)::value] = zr[N - decltype(k)::value];
+        zi[decltype(k)::value] = -zi[N - decltype(k)::value];
+      });
+      fft_reg<N, +1, T>(zr, zi);
+      constexpr double sc = 1.0 / double(n3);
+      static_for<0, N>([&](auto j) { out[decltype(j)::value] = sc * double(zr[decltype(j)::value]); });
     }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-      if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
+    {
+      double lr[N], li[N];
+      const C<double> *x = Lm + b * n3 + r;
+      static_for<0, N>([&](auto k) {
+        const C<double> v = x[decltype(k)::value * n2];
+        lr[decltype(k)::value] = v.re;
+        li[decltype(k)::value] = v.im;
+      });
+      fft_reg<N, +1, double>(lr, li);
+      const double *gb = g + b * n3 + r;
+      static_for<0, N>([&](auto j) {
+        constexpr int jj = decltype(j)::value;
+        out[jj] -= gb[jj * n2] * lr[jj] + li[jj];
+      });
     }
-    tot += dlog[p] * (dwg[b * Nr + p] - red[0] / double(n3));
-    __syncthreads();
+    double *o = df + b * n3 + r;
+    static_for<0, N>([&](auto j) { o[decltype(j)::value * n2] = out[decltype(j)::value]; });
   }
-  if (threadIdx.x == 0) domega[b] = tot;
+};
+
+// loss part of the omega gradient and the final combination:
+// domega[b] = sum_p dlog_p ( dwg[b][p] - (1/N^3) sum_k Re(conj(FG) H) Lam_p(k) ).
+// The spectrum of an item is split into kDomSeg segments of one block each; a
+// block forms x(k) = Re(conj(FG) H)(k) once per point and accumulates x Lam_p
+// for every node p in registers, then reduces each node's sums over the block
+// (wave butterflies, then the four waves in order).
+template <int NRM>
+__global__ __launch_bounds__(256) void k_domega_part(const C<double> *H, const C<double> *FG, const double *lam_p,
+                                                     double *part, int Nr, long n3) {
+  const long b = blockIdx.x / kDomSeg;
+  const int g = blockIdx.x % kDomSeg;
+  const long seg = (n3 + kDomSeg - 1) / kDomSeg;
+  const long k0 = g * seg, k1 = (k0 + seg < n3) ? k0 + seg : n3;
+  double acc[NRM];
+#pragma unroll
+  for (int q = 0; q < NRM; ++q) acc[q] = 0.0;
+  for (long k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
+    const C<double> h = H[b * n3 + k], x = FG[b * n3 + k];
+    const double v = x.re * h.re + x.im * h.im;
+#pragma unroll
+    for (int q = 0; q < NRM; ++q)
+      if (q < Nr) acc[q] += v * lam_p[q * n3 + k];
+  }
+  __shared__ double red[4][NRM];
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+#pragma unroll
+  for (int q = 0; q < NRM; ++q) {
+    double v = acc[q];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) red[wave][q] = v;
+  }
+  __syncthreads();
+  if (int(threadIdx.x) < Nr) {
+    const int q = threadIdx.x;
+    part[blockIdx.x * long(Nr) + q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+  }
+}
+
+__global__ __launch_bounds__(64) void k_domega_final(const double *part, const double *dlog, const double *dwg,
+                                                     double *domega, int Nr, long n3) {
+  const long b = blockIdx.x;
+  __shared__ double t[64];
+  const int q = threadIdx.x;
+  if (q < Nr) {
+    double s = 0.0;
+    for (int g = 0; g < kDomSeg; ++g) s += part[(b * kDomSeg + g) * Nr + q];
+    t[q] = dlog[q] * (dwg[b * Nr + q] - s / double(n3));
+  }
+  __syncthreads();
+  if (q == 0) {
+    double tot = 0.0;
+    for (int r = 0; r < Nr; ++r) tot += t[r];
+    domega[b] = tot;
+  }
+}
+
+static void launch_domega(const C<double> *H, const C<double> *FG, const double *lam_p, const double *dlog,
+                          const double *dwg, double *part, double *domega, long nb, int Nr, long n3,
+                          hipStream_t st) {
+  const dim3 g(unsigned(nb * kDomSeg)), blk(256);
+  switch (mix_width(Nr)) {
+    case 8: hipLaunchKernelGGL((k_domega_part<8>), g, blk, 0, st, H, FG, lam_p, part, Nr, n3); break;
+    case 16: hipLaunchKernelGGL((k_domega_part<16>), g, blk, 0, st, H, FG, lam_p, part, Nr, n3); break;
+    case 24: hipLaunchKernelGGL((k_domega_part<24>), g, blk, 0, st, H, FG, lam_p, part, Nr, n3); break;
+    case 32: hipLaunchKernelGGL((k_domega_part<32>), g, blk, 0, st, H, FG, lam_p, part, Nr, n3); break;
+    case 48: hipLaunchKernelGGL((k_domega_part<48>), g, blk, 0, st, H, FG, lam_p, part, Nr, n3); break;
+    default: hipLaunchKernelGGL((k_domega_part<64>), g, blk, 0, st, H, FG, lam_p, part, Nr, n3); break;
+  }
+  hipLaunchKernelGGL(k_domega_final, dim3(unsigned(nb)), dim3(64), 0, st, part, dlog, dwg, domega, Nr, n3);
 }
 
 // Conservation projection of the cotangent, g -> g - sum_a lam_a phi_a with
@@ -386,7 +484,9 @@ struct Vjp {
     double *gproj = reinterpret_cast<double *>(w + lay.off_a);
     double *dwg = reinterpret_cast<double *>(w + lay.off_d);
     double *pm = reinterpret_cast<double *>(w + lay.off_pm);
+    double *dpart = reinterpret_cast<double *>(w + lay.off_dp);
     const int S = p.nv, np = p.npair(), Nr = p.N_rho, M = p.M;
+    const bool fused_adjoint = std::is_same<T, float>::value && use_fused_adjoint(p);
     qcoll_status s;
     for (long b0 = 0; b0 < batch; b0 += lay.bc) {
       const long nb = (batch - b0 < lay.bc) ? (batch - b0) : lay.bc;
@@ -428,40 +528,60 @@ struct Vjp {
         hipLaunchKernelGGL(k_fill, dim3(nblk(nb * Nr, 256)), dim3(256), 0, st, dwg, nb * Nr, 0.0);
         QC_LAUNCH_CHECK("fill");
       }
-      // gain adjoint, items in sub-chunks of lay.pc items
-      const T scale = T(1.0 / double(n3));
-      for (long ib0 = 0; ib0 < nb; ib0 += lay.pc) {
-        const long ni = (nb - ib0 < lay.pc) ? (nb - ib0) : lay.pc;
-        const long bp0 = ib0 * Nr;
-        const long cnt = ni * Nr;
-        SrcShift<T, N> src{H, reinterpret_cast<const C<T> *>(p.phase), bp0, M, Nr, scale};
-        if ((s = P::template slab<SrcShift<T, N>, DstCplx<T, N>, +1>(src, DstCplx<T, N>{Y}, cnt * M * N, st,
-                                                                      "vjp gain slab")))
+      if (fused_adjoint) {
+        // gain adjoint on chip, one workgroup per (item, p) pair, then the sum
+        // over p of the pairs' half spectra and the inverse along axes 2, 3
+        constexpr int H1 = N / 2 + 1;
+        constexpr long nh = long(H1) * N * N;
+        if ((s = launch_adjoint_fused(p, H, reinterpret_cast<const float *>(Hp), Y, domega ? dwg : nullptr,
+                                      nb * Nr, st)))
           return s;
-        OpAdjPencil<T, N> op{Y, Hp, reinterpret_cast<const T *>(p.wq), domega ? dwg : nullptr, bp0, M};
-        if ((s = P::pencil(op, cnt * N * N, st, "vjp gain pencil"))) return s;
-        TimedLaunch tl("vjp gain acc", st);
-        hipLaunchKernelGGL((k_adj_acc<T, N>), dim3(nblk(ni * N, SPB)), dim3(SPB * N), 0, st, Y,
-                           reinterpret_cast<const C<T> *>(p.phase), Z, ib0, ni, M, Nr);
-        QC_LAUNCH_CHECK("vjp gain acc");
+        {
+          TimedLaunch tl("vjp sum nodes", st);
+          launch_sum_nodes(Y, Z, nb, Nr, nh / 2, n3 / 2, st);
+          QC_LAUNCH_CHECK("vjp sum nodes");
+        }
+        if ((s = P::template slab<SrcCplxHalf<T, N>, DstCplxHalf<T, N>, +1>(
+                 SrcCplxHalf<T, N>{Z}, DstCplxHalf<T, N>{Z}, nb * H1, st, "vjp inverse slab")))
+          return s;
+      } else {
+        // gain adjoint, items in sub-chunks of lay.pc items
+        const T scale = T(1.0 / double(n3));
+        for (long ib0 = 0; ib0 < nb; ib0 += lay.pc) {
+          const long ni = (nb - ib0 < lay.pc) ? (nb - ib0) : lay.pc;
+          const long bp0 = ib0 * Nr;
+          const long cnt = ni * Nr;
+          SrcShift<T, N> src{H, reinterpret_cast<const C<T> *>(p.phase), bp0, M, Nr, scale};
+          if ((s = P::template slab<SrcShift<T, N>, DstCplx<T, N>, +1>(src, DstCplx<T, N>{Y}, cnt * M * N, st,
+                                                                        "vjp gain slab")))
+            return s;
+          OpAdjPencil<T, N> op{Y, Hp, reinterpret_cast<const T *>(p.wq), domega ? dwg : nullptr, bp0, M};
+          if ((s = P::pencil(op, cnt * N * N, st, "vjp gain pencil"))) return s;
+          TimedLaunch tl("vjp gain acc", st);
+          hipLaunchKernelGGL((k_adj_acc<T, N>), dim3(nblk(ni * N, SPB)), dim3(SPB * N), 0, st, Y,
+                             reinterpret_cast<const C<T> *>(p.phase), Z, ib0, ni, M, Nr);
+          QC_LAUNCH_CHECK("vjp gain acc");
+        }
+        // gain inverse (slab pass; the pencil pass is in the assembly)
+        if ((s = P::template slab<SrcCplx<T, N>, DstCplx<T, N>, +1>(SrcCplx<T, N>{Z}, DstCplx<T, N>{Z}, nb * N, st,
+                                                                     "vjp inverse slab")))
+          return s;
       }
-      // gain inverse (slab pass; the pencil pass is in the assembly)
-      if ((s = P::template slab<SrcCplx<T, N>, DstCplx<T, N>, +1>(SrcCplx<T, N>{Z}, DstCplx<T, N>{Z}, nb * N, st,
-                                                                   "vjp inverse slab")))
-        return s;
       // loss adjoint spectrum Lam (H + i FG), inverse slab pass
       if ((s = P64::template slab<SrcLossAdj<N>, DstCplx<double, N>, +1>(
                SrcLossAdj<N>{H64, FG64, reinterpret_cast<const double *>(p.lam)}, DstCplx<double, N>{Lm}, nb * N,
                st, "vjp loss slab")))
         return s;
-      if (df) {
+      if (df && fused_adjoint) {
+        if ((s = P::pencil(OpVjpAssembleHalf<T, N>{Z, Lm, gb, df + b0 * n3}, nb * N * N, st, "vjp assemble")))
+          return s;
+      } else if (df) {
         if ((s = P::pencil(OpVjpAssemble<T, N>{Z, Lm, gb, df + b0 * n3}, nb * N * N, st, "vjp assemble")))
           return s;
       }
       if (domega) {
         TimedLaunch tl("vjp domega", st);
-        hipLaunchKernelGGL(k_domega, dim3(unsigned(nb)), dim3(256), 0, st, H64, FG64, p.lam_p, p.dlog, dwg,
-                           domega + b0, Nr, n3);
+        launch_domega(H64, FG64, p.lam_p, p.dlog, dwg, dpart, domega + b0, nb, Nr, n3, st);
         QC_LAUNCH_CHECK("vjp domega");
       }
     }

@@ -129,3 +129,66 @@ def test_autograd_function():
     df, dw = plan.vjp(f.detach(), g, through_conserve=True, want_domega=True)
     assert torch.allclose(f.grad, df, rtol=0, atol=1e-14 * float(df.abs().max()))
     assert abs(float(om.grad) - float(dw.sum())) <= 1e-12 * abs(float(dw.sum()))
+
+
+@pytest.mark.parametrize("N,L,N_rho,M,batch", [(24, 6.0, 8, 12, 3), (32, 6.0, 8, 12, 2)])
+def test_fused_adjoint_matches_two_pass_and_fp64(N, L, N_rho, M, batch):
+    """FP32 plans run the gain adjoint on chip (one workgroup per (item, node)
+    pair, Hermitian half-spectrum accumulator); the two-pass schedule computes
+    the same df and d omega.  Both against the FP64 plan."""
+    print(f"case fused adjoint N={N}", flush=True)
+    sph = W.sphere_rule(M)
+    f = W.maxwellian_mixture(batch, N, L, 500 + N)
+    g = W.cotangent(f, 501 + N)
+    fg, gg = gpu(f), gpu(g)
+    p64 = qc.Plan(N, L, N_rho, sphere=sph, omega=0.81, precision=qc.QCOLL_FP64)
+    ref, refw = (x.cpu().numpy() for x in p64.vjp(fg, gg, want_df=True, want_domega=True))
+    fused = qc.Plan(N, L, N_rho, sphere=sph, omega=0.81, precision=qc.QCOLL_FP32)
+    two = qc.Plan(N, L, N_rho, sphere=sph, omega=0.81, precision=qc.QCOLL_FP32)
+    two.set_schedule(1)
+    for name, pl in (("fused", fused), ("two-pass", two)):
+        df, dw = (x.cpu().numpy() for x in pl.vjp(fg, gg, want_df=True, want_domega=True))
+        e = rel(df, ref)
+        ew = float(np.max(np.abs(dw - refw) / np.abs(refw)))
+        print(f"{name}: df rel {e:.3e} domega rel {ew:.3e}", flush=True)
+        assert e <= TOL[qc.QCOLL_FP32]
+        assert ew <= 1e-4
+    # the fused adjoint needs no per-term volume: a much smaller workspace
+    assert fused.workspace_bytes(batch, 1) < two.workspace_bytes(batch, 1)
+
+
+def test_fused_adjoint_truncated_plan_matches_oracle():
+    N, L, Nr = 12, 5.0, 8
+    sph = W.sphere_rule(12)
+    f = W.maxwellian_mixture(3, N, L, 81)
+    g = W.cotangent(f, 82)
+    P = spectral.Params(N, L, Nr, sph[0], sph[1], 0.81, svd_tol=1e-6)
+    plan = qc.Plan(N, L, Nr, sphere=sph, omega=0.81, svd_rank=0, svd_tol=1e-6, precision=qc.QCOLL_FP32)
+    df, _ = plan.vjp(gpu(f), gpu(g), through_conserve=True)
+    gp, _ = oc.project(g, N, L)
+    ref = np.stack([adjoint.vjp_f(f[i], gp[i], P) for i in range(3)])
+    e = rel(df.cpu().numpy(), ref)
+    print(f"truncated FP32 fused adjoint: df rel {e:.3e}", flush=True)
+    assert e <= TOL[qc.QCOLL_FP32]
+
+
+def test_fused_adjoint_full_size_against_fp64():
+    """The adjoint-check batch (256 points, 32^3, M = 12, N_rho = 16), FP32 plan
+    with the fused adjoint in the launch configuration the benchmark times,
+    every item against the FP64 plan (itself pinned to the oracle above)."""
+    w = W.WORKLOADS["adjoint_32"]
+    N, L, Nr, M, om = w["N"], w["L"], w["N_rho"], w["M"], w["omega"]
+    sph = W.sphere_rule(M)
+    f = W.mixture_for("adjoint_32")
+    g = W.cotangent(f, 4001)
+    fg, gg = gpu(f), gpu(g)
+    p64 = qc.Plan(N, L, Nr, sphere=sph, omega=om, precision=qc.QCOLL_FP64)
+    ref, refw = p64.vjp(fg, gg, want_df=True, want_domega=True)
+    p32 = qc.Plan(N, L, Nr, sphere=sph, omega=om, precision=qc.QCOLL_FP32)
+    df, dw = p32.vjp(fg, gg, want_df=True, want_domega=True)
+    e = float(((df - ref).abs().amax(dim=(1, 2, 3)) / ref.abs().amax(dim=(1, 2, 3))).max())
+    # g . dQ/domega can nearly cancel for single items: the median is checked
+    ew = float(((dw - refw).abs() / refw.abs().clamp_min(1e-30)).median())
+    print(f"full size FP32 fused adjoint: max item df rel {e:.3e}, median domega rel {ew:.3e}", flush=True)
+    assert e <= TOL[qc.QCOLL_FP32]
+    assert ew <= 1e-4
