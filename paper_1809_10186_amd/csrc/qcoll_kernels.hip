@@ -393,7 +393,7 @@ struct OpGainVss {
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_vss_acc(const C<T> *Y, const T *apq, C<T> *W, long bp0, long npair, int M,
                                                  int Nr) {
-  constexpr int SPB = slab_spb<T, N>();
+  constexpr int SPB = slab_spb2<T, N>();
   constexpr int H1 = N / 2 + 1;
   constexpr long n2 = long(N) * N, n3 = n2 * N, nh = long(H1) * n2;
   __shared__ T sre[SPB][N][N + 1];
@@ -506,7 +506,7 @@ struct Engine {
                                C<double> *LH, const double *fb, double *Qb, long nb, long pc, hipStream_t st) {
     constexpr int H1 = N / 2 + 1;
     constexpr long nh = long(H1) * N * N;
-    constexpr int SPB = slab_spb<T, N>();
+    constexpr int SPB = slab_spb2<T, N>();
     C<T> *Wp = reinterpret_cast<C<T> *>(A);
     const long nbp = nb * p.N_rho;
     const T scale = T(1.0 / double(n3));

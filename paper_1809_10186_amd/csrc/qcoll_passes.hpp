@@ -22,13 +22,12 @@ namespace qcoll {
 template <typename T>
 using C = cplx<T>;
 
-// slabs per workgroup of the generic slab kernel: the first count whose N
-// lanes per slab fill whole waves, else the one that leaves the fewest lanes
-// idle, with the LDS tile within 64 KiB and at most 256 lanes
-template <typename T, int N>
-constexpr int slab_spb() {
+// Slabs per block of the slab kernels, for bytes_per_slab of LDS: the first
+// count whose lanes fill whole waves, else the one that leaves the fewest lanes
+// idle, with the LDS tile within 64 KiB and at most 256 lanes.
+constexpr int spb_for(int N, int bytes_per_slab) {
   int best = 1, best_num = 0, best_den = 1;
-  for (int s = 1; s * N <= 256 && s * 2 * N * (N + 1) * int(sizeof(T)) <= 65536; ++s) {
+  for (int s = 1; s * N <= 256 && s * bytes_per_slab <= 65536; ++s) {
     const int lanes = s * N, waves = (lanes + 63) / 64;
     if (lanes % 64 == 0) return s;
     if (lanes * best_den > best_num * (64 * waves)) {
@@ -40,6 +39,26 @@ constexpr int slab_spb() {
   return best;
 }
 
+constexpr int lane_use_pct(int N, int spb) { return 100 * spb * N / (64 * ((spb * N + 63) / 64)); }
+
+// both components of the slab in LDS at once
+template <typename T, int N>
+constexpr int slab_spb2() {
+  return spb_for(N, 2 * N * (N + 1) * int(sizeof(T)));
+}
+
+// k_slab moves one component at a time through LDS (more barriers, half the
+// tile) where that turns blocks with idle lanes into whole waves (N = 48 in FP32)
+template <typename T, int N>
+constexpr bool slab_split() {
+  return lane_use_pct(N, slab_spb2<T, N>()) < 80 && lane_use_pct(N, spb_for(N, N * (N + 1) * int(sizeof(T)))) == 100;
+}
+
+template <typename T, int N>
+constexpr int slab_spb() {
+  return slab_split<T, N>() ? spb_for(N, N * (N + 1) * int(sizeof(T))) : slab_spb2<T, N>();
+}
+
 // Generic slab kernel: Src(g, r, c) -> C<T> loads element (r, c) of slab g with
 // any prologue; Dst(g, r, c, v) stores.  Slabs g >= nslab are skipped.
 //
@@ -49,11 +68,11 @@ constexpr int slab_spb() {
 // result goes back through LDS so that the stores are column-wise again.  The
 // slab index is fixed per lane, so whatever Src and Dst derive from it is
 // computed once.  Lanes of a slab past the end read slab nslab - 1 (always
-// valid) and store nothing.
-template <typename T, int N, int SIGN, class Src, class Dst, int SPB = slab_spb<T, N>()>
+// valid) and store nothing.  With SPLIT the real and imaginary parts take
+// turns in one tile.
+template <typename T, int N, int SIGN, class Src, class Dst, int SPB = slab_spb<T, N>(),
+          bool SPLIT = slab_split<T, N>()>
 __global__ __launch_bounds__(256) void k_slab(Src src, Dst dst, long nslab) {
-  __shared__ T sre[SPB][N][N + 1];
-  __shared__ T sim[SPB][N][N + 1];
   const int s = int(threadIdx.x) / N, c = int(threadIdx.x) % N;
   const long g = long(blockIdx.x) * SPB + s;
   const long gl = g < nslab ? g : nslab - 1;
@@ -64,26 +83,57 @@ __global__ __launch_bounds__(256) void k_slab(Src src, Dst dst, long nslab) {
     xi[decltype(r)::value] = v.im;
   });
   fft_reg<N, SIGN, T>(xr, xi);
-  static_for<0, N>([&](auto r) {
-    sre[s][decltype(r)::value][c] = xr[decltype(r)::value];
-    sim[s][decltype(r)::value][c] = xi[decltype(r)::value];
-  });
-  __syncthreads();
-  const int row = c;
-  static_for<0, N>([&](auto k) {
-    xr[decltype(k)::value] = sre[s][row][decltype(k)::value];
-    xi[decltype(k)::value] = sim[s][row][decltype(k)::value];
-  });
-  fft_reg<N, SIGN, T>(xr, xi);
-  static_for<0, N>([&](auto k) {
-    sre[s][row][decltype(k)::value] = xr[decltype(k)::value];
-    sim[s][row][decltype(k)::value] = xi[decltype(k)::value];
-  });
-  __syncthreads();
-  if (g < nslab) {
+  if constexpr (SPLIT) {
+    // one tile, one component at a time: column -> row, row FFT, row -> column
+    __shared__ T sb[SPB][N][N + 1];
+    const int row = c;
+    auto to_rows = [&](T *x) {
+      static_for<0, N>([&](auto r) { sb[s][decltype(r)::value][c] = x[decltype(r)::value]; });
+      __syncthreads();
+      static_for<0, N>([&](auto k) { x[decltype(k)::value] = sb[s][row][decltype(k)::value]; });
+      __syncthreads();
+    };
+    auto to_cols = [&](T *x) {
+      static_for<0, N>([&](auto k) { sb[s][row][decltype(k)::value] = x[decltype(k)::value]; });
+      __syncthreads();
+      static_for<0, N>([&](auto r) { x[decltype(r)::value] = sb[s][decltype(r)::value][c]; });
+      __syncthreads();
+    };
+    to_rows(xr);
+    to_rows(xi);
+    fft_reg<N, SIGN, T>(xr, xi);
+    to_cols(xr);
+    to_cols(xi);
+    if (g < nslab) {
+      static_for<0, N>([&](auto r) {
+        dst(g, decltype(r)::value, c, C<T>{xr[decltype(r)::value], xi[decltype(r)::value]});
+      });
+    }
+    return;
+  } else {
+    __shared__ T sre[SPB][N][N + 1];
+    __shared__ T sim[SPB][N][N + 1];
     static_for<0, N>([&](auto r) {
-      dst(g, decltype(r)::value, c, C<T>{sre[s][decltype(r)::value][c], sim[s][decltype(r)::value][c]});
+      sre[s][decltype(r)::value][c] = xr[decltype(r)::value];
+      sim[s][decltype(r)::value][c] = xi[decltype(r)::value];
     });
+    __syncthreads();
+    const int row = c;
+    static_for<0, N>([&](auto k) {
+      xr[decltype(k)::value] = sre[s][row][decltype(k)::value];
+      xi[decltype(k)::value] = sim[s][row][decltype(k)::value];
+    });
+    fft_reg<N, SIGN, T>(xr, xi);
+    static_for<0, N>([&](auto k) {
+      sre[s][row][decltype(k)::value] = xr[decltype(k)::value];
+      sim[s][row][decltype(k)::value] = xi[decltype(k)::value];
+    });
+    __syncthreads();
+    if (g < nslab) {
+      static_for<0, N>([&](auto r) {
+        dst(g, decltype(r)::value, c, C<T>{sre[s][decltype(r)::value][c], sim[s][decltype(r)::value][c]});
+      });
+    }
   }
 }
 

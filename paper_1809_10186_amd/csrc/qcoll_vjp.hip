@@ -152,7 +152,7 @@ struct OpAdjPencil {
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_adj_acc(const C<T> *Y, const C<T> *phase, C<T> *Z, long ib0, long ni,
                                                  int M, int Nr) {
-  constexpr int SPB = slab_spb<T, N>();
+  constexpr int SPB = slab_spb2<T, N>();
   constexpr long n2 = long(N) * N, n3 = n2 * N;
   __shared__ T sre[SPB][N][N + 1];
   __shared__ T sim[SPB][N][N + 1];
@@ -466,7 +466,7 @@ struct Vjp {
   using P = Passes<T, N>;
   using P64 = Passes<double, N>;
   static constexpr long n3 = P::n3;
-  static constexpr int SPB = slab_spb<T, N>();
+  static constexpr int SPB = slab_spb2<T, N>();
 
   static qcoll_status run(const Plan &p, int64_t batch, const double *f, const double *g_in, double *df,
                           double *domega, bool through, void *ws, const Layout &lay, hipStream_t st) {
