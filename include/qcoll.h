@@ -135,10 +135,10 @@ qcoll_status qcoll_plan_radial(qcoll_plan plan, double *host_rho, double *host_w
  * plan; rebuilds the kernel tables synchronously.  ENOTSUP for truncated plans. */
 qcoll_status qcoll_plan_set_omega(qcoll_plan plan, double omega);
 
-/* Hot-loop schedule: 0 = automatic (fused single-pass kernel where it is
- * available: FP32 with N <= 32; otherwise two passes over HBM), 1 = force the
- * two-pass schedule, 2 = require the fused kernel (ENOTSUP where it is not
- * available).  Results agree to rounding; workspace sizes depend on it.
+/* Hot-loop schedule: 0 = automatic (on-chip kernel where it is available:
+ * FP32 with N <= 32, FP64 with N = 16; otherwise two passes over HBM),
+ * 1 = force the two-pass schedule, 2 = require the on-chip kernel (ENOTSUP
+ * where it is not available).  Results agree to rounding; workspace sizes depend on it.
  * The schedule requested here also selects the gain adjoint of qcoll_vjp
  * (fused unless 1 was requested; the autotuner's choice of the forward
  * schedule does not change it). */

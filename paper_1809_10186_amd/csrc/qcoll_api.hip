@@ -147,8 +147,8 @@ qcoll_status qcoll_plan_set_omega(qcoll_plan plan, double omega) {
 qcoll_status qcoll_plan_set_schedule(qcoll_plan plan, int32_t schedule) {
   if (!plan) return fail(QCOLL_EINVAL, "plan is NULL");
   if (schedule < 0 || schedule > 2) return fail(QCOLL_EINVAL, "schedule must be 0, 1 or 2");
-  if (schedule == 2 && !qcoll::fused_gain_supported(plan->p.N, plan->p.precision))
-    return fail(QCOLL_ENOTSUP, "the fused gain kernel needs FP32 and N <= 32");
+  if (schedule == 2 && !qcoll::onchip_schedule_supported(plan->p.N, plan->p.precision))
+    return fail(QCOLL_ENOTSUP, "the on-chip gain kernels need FP32 with N <= 32 or FP64 with N = 16");
   plan->p.schedule = schedule;
   plan->p.schedule_user = schedule;
   return QCOLL_OK;

@@ -269,7 +269,7 @@ size_t qcoll_autotune_workspace_bytes(qcoll_plan plan, int64_t batch) {
   size_t mx = 0;
   for (int sch : {1, 2})
     for (int ck : tune_chunks(batch)) {
-      if (sch == 2 && !qcoll::fused_gain_supported(p.N, p.precision)) continue;
+      if (sch == 2 && !qcoll::onchip_schedule_supported(p.N, p.precision)) continue;
       p.schedule = sch;
       p.chunk = ck;
       mx = std::max(mx, qcoll::make_layout(p, batch, 0).total);
@@ -302,7 +302,7 @@ qcoll_status qcoll_autotune(qcoll_plan plan, int64_t batch, const double *f, dou
       if (bar == std::string::npos || line.substr(0, bar) != key) continue;
       int sch = 0, ck = 0;
       if (std::sscanf(line.c_str() + bar + 1, "%d %d", &sch, &ck) == 2 &&
-          (sch != 2 || qcoll::fused_gain_supported(p.N, p.precision))) {
+          (sch != 2 || qcoll::onchip_schedule_supported(p.N, p.precision))) {
         p.schedule = sch;
         p.chunk = ck;
         if (host_schedule) *host_schedule = sch;
@@ -322,7 +322,7 @@ qcoll_status qcoll_autotune(qcoll_plan plan, int64_t batch, const double *f, dou
   qcoll_status rc = QCOLL_OK;
   for (int sch : {2, 1})
     for (int ck : tune_chunks(batch)) {
-      if (sch == 2 && !qcoll::fused_gain_supported(p.N, p.precision)) continue;
+      if (sch == 2 && !qcoll::onchip_schedule_supported(p.N, p.precision)) continue;
       p.schedule = sch;
       p.chunk = ck;
       const qcoll::Layout lay = qcoll::make_layout(p, batch, 0);

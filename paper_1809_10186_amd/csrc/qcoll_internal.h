@@ -87,6 +87,14 @@ qcoll_status launch_dg_contract(const double *A, const double *X, double *Y, lon
 bool fused_gain_supported(int N, int precision);
 bool use_fused_gain(const Plan &p);
 qcoll_status launch_gain_fused(const Plan &p, const void *H, void *W, long nbp, hipStream_t st);
+// FP64 gain loop on chip (N = 16): A_p of every (item, node) pair
+bool gain_q64_supported(int N, int precision);
+bool use_gain_q64(const Plan &p);
+qcoll_status launch_gain_q64(const Plan &p, const void *H, double *A, long nbp, hipStream_t st);
+// schedule 2 exists for this grid and precision (FP32 fused kernel or FP64 on-chip gain)
+inline bool onchip_schedule_supported(int N, int precision) {
+  return fused_gain_supported(N, precision) || gain_q64_supported(N, precision);
+}
 // sum over the N_rho per-node spectra of each item (FP32 complex, float4 units)
 void launch_sum_nodes(const void *W, void *out, long nitems, int Nr, long n_in, long n_out, hipStream_t st);
 // fused gain adjoint of the VJP (FP32, N <= 32, VHS kernels)

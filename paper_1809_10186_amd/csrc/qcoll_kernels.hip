@@ -465,6 +465,9 @@ struct Engine {
   static qcoll_status gain_terms(const Plan &p, const C<T> *H, T *A, C<T> *Y, long nb, long pc,
                                  hipStream_t st) {
     const long nbp = nb * p.N_rho;
+    if constexpr (std::is_same<T, double>::value) {
+      if (use_gain_q64(p)) return launch_gain_q64(p, H, A, nbp, st);
+    }
     const T scale = T(1.0 / double(n3));
     for (long bp0 = 0; bp0 < nbp; bp0 += pc) {
       const long cnt = (nbp - bp0 < pc) ? (nbp - bp0) : pc;
@@ -837,7 +840,8 @@ Layout make_layout(const Plan &p, int64_t batch, int op) {
   l.off_w = o; o += half ? 0 : al(size_t(l.bc) * p.npair() * n3 * 2 * es);
   l.off_t = o; o += al(size_t(l.bc) * n3 * 2 * es);
   l.off_l = o; o += al(size_t(l.bc) * n3 * 2 * sizeof(double));
-  l.off_y = o; o += fused ? 0 : al(size_t(l.pc) * p.M * n3 * 2 * es);
+  const bool q64 = use_gain_q64(p) && !bil;   // FP64 gain on chip: no per-term volumes
+  l.off_y = o; o += (fused || q64) ? 0 : al(size_t(l.pc) * p.M * n3 * 2 * es);
   if (bil) {
     l.off_hg = o; o += al(size_t(l.bc) * n3 * 2 * es);
     l.off_h64g = o; o += al(size_t(l.bc) * n3 * 2 * sizeof(double));

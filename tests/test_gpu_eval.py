@@ -192,8 +192,41 @@ def test_schedule_requests_are_validated():
     with pytest.raises(qc.QcollError) as e:
         plan.set_schedule(2)
     assert e.value.code == 2
-    plan64 = qc.Plan(16, 6.0, 2, sphere=None, omega=0.81, precision=qc.QCOLL_FP64)
+    plan64 = qc.Plan(12, 6.0, 2, sphere=None, omega=0.81, precision=qc.QCOLL_FP64)
     with pytest.raises(qc.QcollError):
         plan64.set_schedule(2)
     with pytest.raises(qc.QcollError):
         plan64.set_schedule(5)
+    # FP64 on-chip gain kernel: N = 16 only
+    qc.Plan(16, 6.0, 2, sphere=None, omega=0.81, precision=qc.QCOLL_FP64).set_schedule(2)
+    with pytest.raises(qc.QcollError):
+        qc.Plan(32, 6.0, 2, sphere=None, omega=0.81, precision=qc.QCOLL_FP64).set_schedule(2)
+
+
+def test_fp64_onchip_gain_matches_oracle_and_two_pass():
+    """FP64 plans at N = 16 run the gain loop on chip (one workgroup per
+    (item, node) pair and residue class of j2 mod 4, pruned first transform);
+    the two-pass schedule computes the same Q to rounding.  Three items against
+    the oracle, then 70 items (two chunks, ragged tail) against the two-pass
+    schedule."""
+    N, L, N_rho, M = 16, 6.0, 8, 12
+    print("case fp64 on-chip gain N=16", flush=True)
+    sph = W.sphere_rule(M)
+    P = spectral.Params(N, L, N_rho, sph[0], sph[1], 0.81)
+    onchip = qc.Plan(N, L, N_rho, sphere=sph, omega=0.81, precision=qc.QCOLL_FP64)
+    two = qc.Plan(N, L, N_rho, sphere=sph, omega=0.81, precision=qc.QCOLL_FP64)
+    two.set_schedule(1)
+    f = W.maxwellian_mixture(3, N, L, 616, noise=0.05)
+    ref = spectral.collide_batch(f, P)
+    fg = gpu(f)
+    Q1 = onchip.eval(fg).cpu().numpy()
+    Q2 = two.eval(fg).cpu().numpy()
+    e1, e2, e12 = rel_linf(Q1, ref), rel_linf(Q2, ref), rel_linf(Q1, Q2)
+    print(f"on-chip {e1:.3e} two-pass {e2:.3e} between {e12:.3e}", flush=True)
+    assert e1 <= 1e-12 and e2 <= 1e-12 and e12 <= 1e-13
+    # no per-term volumes: a much smaller workspace
+    assert onchip.workspace_bytes(3) < two.workspace_bytes(3)
+    fb = gpu(W.maxwellian_mixture(70, N, L, 617, noise=0.05))
+    e = rel_linf(onchip.eval(fb).cpu().numpy(), two.eval(fb).cpu().numpy())
+    print(f"70 items: on-chip vs two-pass {e:.3e}", flush=True)
+    assert e <= 1e-13
