@@ -192,3 +192,38 @@ def test_fused_adjoint_full_size_against_fp64():
     print(f"full size FP32 fused adjoint: max item df rel {e:.3e}, median domega rel {ew:.3e}", flush=True)
     assert e <= TOL[qc.QCOLL_FP32]
     assert ew <= 1e-4
+
+
+@pytest.mark.parametrize("N_rho", [32, 40, 64])
+def test_many_radial_nodes_eval_and_vjp(N_rho):
+    """Up to the maximum N_rho = 64 (the register widths 32, 48 and 64 of the
+    low-rank mixing, unpacking and omega-gradient kernels): eval of a full and
+    an SVD-truncated plan in both precisions, and the VJP in f and omega,
+    against the oracle at N = 8."""
+    N, L, M = 8, 4.0, 6
+    print(f"case N_rho={N_rho}", flush=True)
+    sph = W.sphere_rule(M)
+    f = W.maxwellian_mixture(3, N, L, 700 + N_rho)
+    g = W.cotangent(f, 701 + N_rho)
+    P = spectral.Params(N, L, N_rho, sph[0], sph[1], 0.81)
+    Pt = spectral.Params(N, L, N_rho, sph[0], sph[1], 0.81, svd_tol=1e-3)
+    ref = spectral.collide_batch(f, P)
+    reft = spectral.collide_batch(f, Pt)
+    for prec in (qc.QCOLL_FP64, qc.QCOLL_FP32):
+        full = qc.Plan(N, L, N_rho, sphere=sph, omega=0.81, precision=prec)
+        trunc = qc.Plan(N, L, N_rho, sphere=sph, omega=0.81, svd_rank=0, svd_tol=1e-3, precision=prec)
+        trunc.set_schedule(1)   # the two-pass low-rank stage: mix to the rank-S basis
+        assert trunc.info()["rank"] == Pt.rank
+        tol = 1e-12 if prec == qc.QCOLL_FP64 else 2e-5
+        e = rel(full.eval(gpu(f)).cpu().numpy(), ref)
+        et = rel(trunc.eval(gpu(f)).cpu().numpy(), reft)
+        df, dw = full.vjp(gpu(f), gpu(g), want_df=True, want_domega=True)
+        rdf = np.stack([adjoint.vjp_f(f[i], g[i], P) for i in range(3)])
+        rdw = np.array([adjoint.vjp_omega(f[i], g[i], P) for i in range(3)])
+        ed = rel(df.cpu().numpy(), rdf)
+        ew = float(np.max(np.abs(dw.cpu().numpy() - rdw) / np.abs(rdw)))
+        print(f"prec={prec} rank={Pt.rank}: eval {e:.3e} truncated {et:.3e} df {ed:.3e} domega {ew:.3e}",
+              flush=True)
+        assert e <= tol and et <= tol
+        assert ed <= TOL[prec]
+        assert ew <= (1e-10 if prec == qc.QCOLL_FP64 else 1e-4)
