@@ -571,12 +571,12 @@ struct Engine {
       const long nb = (batch - b0 < lay.bc) ? (batch - b0) : lay.bc;
       const double *fb = f + b0 * n3;
       qcoll_status s;
-      // spectrum of f in FP64 (shared by the gain and the loss)
-      if ((s = Passes<double, N>::forward(fb, H64, nb, st))) return s;
+      // spectrum of f in FP64 (shared by the gain and the loss), and its copy
+      // in the working precision for the gain
       if constexpr (!std::is_same<T, double>::value) {
-        TimedLaunch tl("cast", st);
-        hipLaunchKernelGGL(k_cast<T>, dim3(nblk(nb * n3, 256)), dim3(256), 0, st, H64, H, nb * n3);
-        QC_LAUNCH_CHECK("cast");
+        if ((s = Passes<double, N>::template forward_to<T>(fb, H64, H, nb, st))) return s;
+      } else {
+        if ((s = Passes<double, N>::forward(fb, H64, nb, st))) return s;
       }
       if (p.is_vss()) {
         if ((s = eval_vss(p, H, H64, A, Y, TA, LH, fb, Q + b0 * n3, nb, lay.pc, st))) return s;
@@ -585,12 +585,7 @@ struct Engine {
       if (g) {
         // bilinear Q(f, g): gain from both spectra, loss f * ifft(Lambda g^)
         const double *gb = g + b0 * n3;
-        if ((s = Passes<double, N>::forward(gb, H64g, nb, st))) return s;
-        {
-          TimedLaunch tl("cast", st);
-          hipLaunchKernelGGL(k_cast<T>, dim3(nblk(nb * n3, 256)), dim3(256), 0, st, H64g, Hg, nb * n3);
-          QC_LAUNCH_CHECK("cast");
-        }
+        if ((s = Passes<double, N>::template forward_to<T>(gb, H64g, Hg, nb, st))) return s;
         if ((s = gain_terms2(p, H, Hg, A, Y, Yg, nb, lay.pc, st))) return s;
       } else if constexpr (std::is_same<T, float>::value) {
         if (use_fused_gain(p)) {

@@ -197,6 +197,30 @@ struct SrcShift {
   }
 };
 
+// forward pencil pass in place (first axis), plus a copy rounded to U
+template <typename T, typename U, int N>
+struct OpPencilForwardTo {
+  C<T> *X;
+  C<U> *XU;
+  __device__ void operator()(long v, int r) const {
+    constexpr long n2 = long(N) * N, n3 = n2 * N;
+    C<T> *x = X + v * n3 + r;
+    C<U> *xu = XU + v * n3 + r;
+    T xr[N], xi[N];
+    static_for<0, N>([&](auto k) {
+      const C<T> e = x[decltype(k)::value * n2];
+      xr[decltype(k)::value] = e.re;
+      xi[decltype(k)::value] = e.im;
+    });
+    fft_reg<N, -1, T>(xr, xi);
+    static_for<0, N>([&](auto k) {
+      constexpr int kk = decltype(k)::value;
+      x[kk * n2] = C<T>{xr[kk], xi[kk]};
+      xu[kk * n2] = C<U>{U(xr[kk]), U(xi[kk])};
+    });
+  }
+};
+
 // forward pencil pass in place (first axis)
 template <typename T, int N, int SIGN>
 struct OpPencilInPlace {
@@ -214,13 +238,6 @@ struct OpPencilInPlace {
     static_for<0, N>([&](auto k) { x[decltype(k)::value * n2] = C<T>{xr[decltype(k)::value], xi[decltype(k)::value]}; });
   }
 };
-
-// FP64 spectrum -> working precision
-template <typename T>
-__global__ void k_cast(const C<double> *in, C<T> *out, long n) {
-  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = C<T>{T(in[i].re), T(in[i].im)};
-}
 
 inline unsigned nblk(long n, int b) { return unsigned((n + b - 1) / b); }
 
@@ -265,6 +282,16 @@ struct Passes {
     if ((s = slab<SrcReal<T, N>, DstCplx<T, N>, -1>(SrcReal<T, N>{f}, DstCplx<T, N>{H}, nb * N, st, "forward slab")))
       return s;
     return pencil(OpPencilInPlace<T, N, -1>{H}, nb * N * N, st, "forward pencil");
+  }
+
+  // the same, also storing a copy of the spectrum rounded to U (the pencil
+  // pass writes both, so the copy costs no extra read)
+  template <typename U>
+  static qcoll_status forward_to(const double *f, C<T> *H, C<U> *HU, long nb, hipStream_t st) {
+    qcoll_status s;
+    if ((s = slab<SrcReal<T, N>, DstCplx<T, N>, -1>(SrcReal<T, N>{f}, DstCplx<T, N>{H}, nb * N, st, "forward slab")))
+      return s;
+    return pencil(OpPencilForwardTo<T, U, N>{H, HU}, nb * N * N, st, "forward pencil");
   }
 
 };

@@ -501,18 +501,12 @@ struct Vjp {
         gb = gproj;
       }
       // FP64 spectra of f, g and f g
-      if ((s = P64::forward(fb, H64, nb, st))) return s;
-      if ((s = P64::forward(gb, G64, nb, st))) return s;
+      if ((s = P64::template forward_to<T>(fb, H64, H, nb, st))) return s;
+      if ((s = P64::template forward_to<T>(gb, G64, GT, nb, st))) return s;
       if ((s = P64::template slab<SrcProd<N>, DstCplx<double, N>, -1>(SrcProd<N>{fb, gb}, DstCplx<double, N>{FG64},
                                                                     nb * N, st, "vjp fg slab")))
         return s;
       if ((s = P64::pencil(OpPencilInPlace<double, N, -1>{FG64}, nb * N * N, st, "vjp fg pencil"))) return s;
-      {
-        TimedLaunch tl("cast", st);
-        hipLaunchKernelGGL(k_cast<T>, dim3(nblk(nb * n3, 256)), dim3(256), 0, st, H64, H, nb * n3);
-        hipLaunchKernelGGL(k_cast<T>, dim3(nblk(nb * n3, 256)), dim3(256), 0, st, G64, GT, nb * n3);
-        QC_LAUNCH_CHECK("cast");
-      }
       // h_p = C_p g: packed inverse transforms of (V_2s + i V_2s+1) G^, then unpack + mix
       if ((s = P::template slab<SrcVPair<T, N>, DstCplx<T, N>, +1>(
                SrcVPair<T, N>{GT, reinterpret_cast<const T *>(p.V), np}, DstCplx<T, N>{R}, nb * np * N, st,
