@@ -68,6 +68,7 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_adj_fused(const cplx<float
   // instead of being held in scalar registers across the whole term
   cplx<float> *b1s = reinterpret_cast<cplx<float> *>(lds + AdjGeom<N>::work);
   for (int t = threadIdx.x; t < M * N; t += NL) b1s[t] = phase[size_t(p * M + t / N) * 3 * N + t % N];
+  __syncthreads();
 
   const int lane = threadIdx.x;
   const int hi = lane / N, lo = lane % N;
@@ -94,9 +95,6 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_adj_fused(const cplx<float
   const __amdgpu_buffer_rsrc_t hpr = make_rsrc(Hp + bp * n3, unsigned(n3 * sizeof(float)));
   for (int q = 0; q < M; ++q) {
     const cplx<float> *ph = phase + size_t(p * M + q) * 3 * N;
-    // the previous term's partner reads cross waves: finish them before the
-    // A -> B writes of this term
-    __syncthreads();
     float zr[1][N], zi[1][N];
     // stage A, lane (k2, k3): c_s(k) = Re(b1 b2 b3) + Im(b1 b2 b3)
     const cplx<float> b2 = ph[N + hi], b3 = ph[2 * N + lo];
@@ -113,6 +111,10 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_adj_fused(const cplx<float
       zi[0][kk] = v.im * c;
     });
     fft_reg<N, +1, float>(zr[0], zi[0]);
+    // the previous term's partner reads cross waves: finish them before the
+    // A -> B writes of this term (stage A above reads only the b1 rows, which
+    // the loop never writes)
+    __syncthreads();
     // A -> B across waves; when the B -> C transpose after it stays in own
     // rows, the barrier after the imaginary-part reads is not needed
     lds_transpose<N, 1>(lds, zr, wa1, ra1);

@@ -83,10 +83,6 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<floa
   const __amdgpu_buffer_rsrc_t hr = make_rsrc(H + b * n3, unsigned(n3 * sizeof(cplx<float>)));
   for (int q = 0; q < M; ++q) {
     const cplx<float> *ph = phase + size_t(p * M + q) * 3 * N;
-    // the previous iteration's last reads (wave-local B -> C) must finish
-    // before this iteration's A -> B writes reach other waves' rows (the VSS
-    // iteration ends with a cross-wave transpose and its own barrier)
-    if constexpr (G::WAVE_BC && !VSS) __syncthreads();
     float zr[PPL][N], zi[PPL][N];
     // stage A: lane (k2, k3) = (hi, lo); c(k1) = Re(b1 b23) + Im(b1 b23),
     // scaled by sqrt(w_q) (the weights are positive), so that the product
@@ -109,7 +105,13 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<floa
       });
       fft_reg<N, +1, float>(zr[u], zi[u]);
     });
-    // A -> B: element (j1, k2, k3) at j1*S1 + k2*N + k3
+    // A -> B: element (j1, k2, k3) at j1*S1 + k2*N + k3.  The previous
+    // iteration's last reads (wave-local B -> C) must finish before these
+    // writes reach other waves' rows; stage A above touches no LDS, so the
+    // barrier sits here and a wave that is done with its product starts the
+    // next term's loads and first transform while others finish theirs (the
+    // VSS iteration ends with a cross-wave transpose and its own barrier).
+    if constexpr (G::WAVE_BC && !VSS) __syncthreads();
     if constexpr (G::WAVE_BC) {
       // A -> B crosses waves: barrier after the writes; the barrier after the
       // imaginary-part reads is not needed (B -> C below stays in own rows)
