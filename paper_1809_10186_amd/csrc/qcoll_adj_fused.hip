@@ -153,7 +153,7 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_adj_fused(const cplx<float
     transpose_bc(zi, ra2, wa2);
     fft_reg<N, -1, float>(zr[0], zi[0]);
     lds_transpose<N, 1>(lds, zr, ra1, wa1);
-    lds_transpose<N, 1>(lds, zi, ra1, wa1);
+    lds_transpose<N, 1, false>(lds, zi, ra1, wa1);   // closing barrier: before the exchange writes
     fft_reg<N, -1, float>(zr[0], zi[0]);
     // lane (k2, k3): c_s(k) P(k), then the values at k1 = -s (s = 0..N/2) to the partner
     static_for<0, N>([&](auto k) {
@@ -163,6 +163,7 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_adj_fused(const cplx<float
       zr[0][kk] *= c;
       zi[0][kk] *= c;
     });
+    __syncthreads();
     static_for<0, H1>([&](auto s) {
       constexpr int ss = decltype(s)::value;
       constexpr int src = (N - ss) % N;

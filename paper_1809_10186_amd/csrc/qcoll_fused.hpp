@@ -34,8 +34,10 @@ struct FusedGeom {
   static constexpr size_t lds_bytes = size_t(N) * S1 * sizeof(float);
 };
 
-// move one component (re or im) of every pencil of the lane through LDS
-template <int N, int PPL, class WA, class RA>
+// move one component (re or im) of every pencil of the lane through LDS; with
+// TAIL = false the barrier after the reads is left to the caller (the tile
+// must not be written again before one)
+template <int N, int PPL, bool TAIL = true, class WA, class RA>
 __device__ __forceinline__ void lds_transpose(float *lds, float (*v)[N], WA wa, RA ra) {
   static_for<0, PPL>([&](auto u) {
     static_for<0, N>([&](auto i) {
@@ -48,7 +50,7 @@ __device__ __forceinline__ void lds_transpose(float *lds, float (*v)[N], WA wa, 
       v[decltype(u)::value][decltype(i)::value] = lds[ra(decltype(u)::value, decltype(i)::value)];
     });
   });
-  __syncthreads();
+  if constexpr (TAIL) __syncthreads();
 }
 
 // Same transpose within one wave: every address a lane writes or reads lies in

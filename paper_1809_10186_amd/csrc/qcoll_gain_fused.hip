@@ -106,12 +106,12 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<floa
       fft_reg<N, +1, float>(zr[u], zi[u]);
     });
     // A -> B: element (j1, k2, k3) at j1*S1 + k2*N + k3.  The previous
-    // iteration's last reads (wave-local B -> C) must finish before these
-    // writes reach other waves' rows; stage A above touches no LDS, so the
-    // barrier sits here and a wave that is done with its product starts the
-    // next term's loads and first transform while others finish theirs (the
-    // VSS iteration ends with a cross-wave transpose and its own barrier).
-    if constexpr (G::WAVE_BC && !VSS) __syncthreads();
+    // iteration's last reads (wave-local B -> C, or in VSS mode the cross-wave
+    // B -> A without its closing barrier) must finish before these writes
+    // reach other waves' rows; stage A above touches no LDS, so the barrier
+    // sits here and a wave that is done with the previous term starts the
+    // next term's loads and first transform while others finish theirs.
+    if constexpr (G::WAVE_BC || VSS) __syncthreads();
     if constexpr (G::WAVE_BC) {
       // A -> B crosses waves: barrier after the writes; the barrier after the
       // imaginary-part reads is not needed (B -> C below stays in own rows)
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<floa
       }
       static_for<0, PPL>([&](auto u) { fft_reg<N, -1, float>(zr[decltype(u)::value], zi[decltype(u)::value]); });
       lds_transpose<N, PPL>(lds, zr, ra1, wa1);
-      lds_transpose<N, PPL>(lds, zi, ra1, wa1);
+      lds_transpose<N, PPL, false>(lds, zi, ra1, wa1);   // closing barrier: before the next A -> B
       const float *a = apq + size_t(p * M + q) * (size_t(H1) * n2);
       static_for<0, PPL>([&](auto uu) {
         constexpr int u = decltype(uu)::value;
