@@ -138,6 +138,18 @@ def test_error_paths_on_device():
     assert code == 1
     assert L.qcoll_eval(plan._h, 0, None, None, None, 0, None) == 0
     assert L.qcoll_eval(plan._h, -1, None, None, None, 0, None) == 1
+    # every compute entry point: an empty batch is a no-op, a negative one is refused
+    empty = {
+        "qcoll_eval_bilinear": lambda n: L.qcoll_eval_bilinear(plan._h, n, None, None, None, None, 0, None),
+        "qcoll_conserve": lambda n: L.qcoll_conserve(plan._h, n, None, None, None),
+        "qcoll_moments": lambda n: L.qcoll_moments(plan._h, n, None, None, None),
+        "qcoll_vjp": lambda n: L.qcoll_vjp(plan._h, n, None, None, None, None, 0, None, 0, None),
+        "qcoll_dg_collide": lambda n: L.qcoll_dg_collide(plan._h, n, 3, 3, None, None, None, None, 0, None, 0,
+                                                         None),
+    }
+    for name, call in empty.items():
+        assert call(0) == 0, name
+        assert call(-1) == 1, name
 
 
 def test_dg1d_full_size_sampled_items():
