@@ -72,8 +72,6 @@ qcoll_status launch_eval(const Plan &p, int64_t batch, const double *f, double *
 qcoll_status launch_eval2(const Plan &p, int64_t batch, const double *f, const double *g, double *Q, void *ws,
                           const Layout &lay, hipStream_t st);
 qcoll_status launch_conserve(const Plan &p, int64_t batch, double *Q, double *mom, hipStream_t st);
-qcoll_status launch_project(const Plan &p, int64_t batch, const double *in, double *out,
-                            hipStream_t st);
 qcoll_status launch_moments(const Plan &p, int64_t batch, const double *f, double *out,
                             hipStream_t st);
 qcoll_status launch_vjp(const Plan &p, int64_t batch, const double *f, const double *g,
