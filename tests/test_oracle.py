@@ -577,3 +577,36 @@ def test_rkdg_exact_and_collocated_collision_forms_agree_on_uniform_state():
     dc = _dg1d(2, 2, N=N, L=L, inv_kn=1.0, coll="collocation")
     Ce, Cc = de.collision(F), dc.collision(F)
     assert np.abs(Ce - Cc).max() <= 1e-12 * np.abs(Cc).max()
+
+
+def test_kernel_table_truncation_closed_form():
+    """The SVD truncation of the gain-weight table (a9) on a table built from
+    known factors: alpha = sum_i s_i u_i v_i^T with orthonormal u, v and
+    s = (10, 4, 1e-3, 1e-9, 0).  The tolerance fixes the rank, and the result is
+    the sum of the kept terms; the residual is orthogonal to it (Frobenius), and
+    no random rank-r approximation is closer (Eckart-Young)."""
+    rng = np.random.default_rng(7)
+    m, N = 5, 4
+    U, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    V, _ = np.linalg.qr(rng.standard_normal((N ** 3, m)))
+    s = np.array([10.0, 4.0, 1e-3, 1e-9, 0.0])
+    A = (U * s) @ V.T
+    alpha = A.reshape(m, N, N, N)
+    for tol, r in ((1e-6, 3), (1e-2, 2), (0.5, 1)):
+        At, rank = kernel.truncate_alpha(alpha, svd_tol=tol)
+        assert rank == r
+        ref = (U[:, :r] * s[:r]) @ V[:, :r].T
+        At = At.reshape(m, -1)
+        assert np.abs(At - ref).max() <= 1e-12 * np.abs(A).max()
+        R = A - At
+        assert abs(np.sum(At * R)) <= 1e-12 * np.sum(A * A)
+        assert abs(np.sum(A * A) - np.sum(At * At) - np.sum(R * R)) <= 1e-12 * np.sum(A * A)
+        err = np.linalg.norm(R)
+        for _ in range(20):
+            Q, _ = np.linalg.qr(rng.standard_normal((m, r)))
+            assert err <= np.linalg.norm(A - Q @ (Q.T @ A)) + 1e-12
+    # a fixed rank, and the full rank reproduces the table
+    At, rank = kernel.truncate_alpha(alpha, svd_rank=2)
+    assert rank == 2 and np.abs(At.reshape(m, -1) - (U[:, :2] * s[:2]) @ V[:, :2].T).max() <= 1e-12 * 10
+    At, rank = kernel.truncate_alpha(alpha, svd_rank=m)
+    assert rank == m and np.abs(At - alpha).max() <= 1e-13 * 10
