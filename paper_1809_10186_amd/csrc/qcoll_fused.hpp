@@ -1,6 +1,7 @@
-// Building blocks of the fused kernels (FP32, N <= 32): one workgroup of N^2
-// lanes owns a whole N^3 complex volume, one pencil per lane, and changes the
-// pencil axis by transposes through one LDS tile.
+// Building blocks of the on-chip kernels.  The FP32 fused kernels (N <= 32):
+// one workgroup of N^2 lanes owns a whole N^3 complex volume, one pencil per
+// lane, and changes the pencil axis by transposes through one LDS tile; the
+// FP64 kernel shares the XCD-aware block numbering.
 #pragma once
 #include <hip/hip_runtime.h>
 

@@ -11,10 +11,13 @@
 //   g . dQ/d omega = sum_p dlog_p ( <h_p, A_p> - <f g, Lam~_p f> ),
 // A_p = sum_q w_q t1 t2, and the loss part is a Fourier-space dot product.
 //
-// Passes per (item, p, q): the forward slab pass of the hot loop, a pencil pass
-// that inverts along axis 1, forms w_q h_p conj(u), accumulates <h_p, A_p> and
-// transforms back along axis 1, and a slab pass that transforms the two inner
-// axes forward and accumulates c_s * (.) for every (p, q) of the item.
+// The gain adjoint runs on chip per (item, p) pair for FP32 plans with N <= 32
+// (k_adj_fused, qcoll_adj_fused.hip).  Otherwise (FP64, N = 48, or the two-pass
+// schedule requested) it takes three passes per (item, p, q): the forward slab
+// pass of the hot loop, a pencil pass that inverts along axis 1, forms
+// w_q h_p conj(u), accumulates <h_p, A_p> and transforms back along axis 1, and
+// a slab pass that transforms the two inner axes forward and accumulates
+// c_s * (.) for every (p, q) of the item.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
