@@ -174,32 +174,36 @@ __device__ __forceinline__ void twiddle_reduced(T &a, T &b) {
 
 // Radix-4 combine of output column k: inputs x_i (i = 0..3) of the sub-transforms,
 // twiddles w_i = exp(SIGN 2 pi i (i k) / N), then the 4-point DFT.  With
-// w_i x_i = f_i x_i', the sums x0 +- w2 x2 and w1 x1 +- w3 x3 take the factors f_i
-// as FMA multipliers; trivial twiddles keep the plain moves.
+// w_i x_i = f_i x_i', the pair x0 +- w2 x2 takes f2 as an FMA multiplier, and the
+// pair w1 x1 +- w3 x3 = f3 (g x1' +- x3') with g = f1 / f3 takes g there and f3 in
+// the four output FMAs, so no factor costs a multiply of its own; trivial
+// twiddles keep the plain moves.
 template <int N, int K, int SIGN, typename T>
 __device__ __forceinline__ void combine4(T *xr, T *xi) {
   using W1 = TwSplit<N, K, SIGN>;
   using W2 = TwSplit<N, 2 * K, SIGN>;
   using W3 = TwSplit<N, 3 * K, SIGN>;
-  T f1 = T(1), f2 = T(1), f3 = T(1);
+  constexpr double F1 = W1::trivial ? 1.0 : W1::f;
+  constexpr double F2 = W2::trivial ? 1.0 : W2::f;
+  constexpr double F3 = W3::trivial ? 1.0 : W3::f;
+  constexpr T g = T(F1 / F3), f2 = T(F2), f3 = T(F3);
   if constexpr (W1::trivial) twiddle<N, K, SIGN, T>(xr[1], xi[1]);
-  else { twiddle_reduced<N, K, SIGN, T>(xr[1], xi[1]); f1 = T(W1::f); }
+  else twiddle_reduced<N, K, SIGN, T>(xr[1], xi[1]);
   if constexpr (W2::trivial) twiddle<N, 2 * K, SIGN, T>(xr[2], xi[2]);
-  else { twiddle_reduced<N, 2 * K, SIGN, T>(xr[2], xi[2]); f2 = T(W2::f); }
+  else twiddle_reduced<N, 2 * K, SIGN, T>(xr[2], xi[2]);
   if constexpr (W3::trivial) twiddle<N, 3 * K, SIGN, T>(xr[3], xi[3]);
-  else { twiddle_reduced<N, 3 * K, SIGN, T>(xr[3], xi[3]); f3 = T(W3::f); }
+  else twiddle_reduced<N, 3 * K, SIGN, T>(xr[3], xi[3]);
   const T s02r = xr[0] + f2 * xr[2], s02i = xi[0] + f2 * xi[2];
   const T d02r = xr[0] - f2 * xr[2], d02i = xi[0] - f2 * xi[2];
-  const T y3r = f3 * xr[3], y3i = f3 * xi[3];
-  const T s13r = f1 * xr[1] + y3r, s13i = f1 * xi[1] + y3i;
-  const T d13r = f1 * xr[1] - y3r, d13i = f1 * xi[1] - y3i;
-  // (SIGN i) * d13
+  const T s13r = g * xr[1] + xr[3], s13i = g * xi[1] + xi[3];
+  const T d13r = g * xr[1] - xr[3], d13i = g * xi[1] - xi[3];
+  // (SIGN i) * d13, still to be scaled by f3
   const T wr = (SIGN > 0) ? -d13i : d13i;
   const T wi = (SIGN > 0) ? d13r : -d13r;
-  xr[0] = s02r + s13r; xi[0] = s02i + s13i;
-  xr[2] = s02r - s13r; xi[2] = s02i - s13i;
-  xr[1] = d02r + wr;   xi[1] = d02i + wi;
-  xr[3] = d02r - wr;   xi[3] = d02i - wi;
+  xr[0] = s02r + f3 * s13r; xi[0] = s02i + f3 * s13i;
+  xr[2] = s02r - f3 * s13r; xi[2] = s02i - f3 * s13i;
+  xr[1] = d02r + f3 * wr;   xi[1] = d02i + f3 * wi;
+  xr[3] = d02r - f3 * wr;   xi[3] = d02i - f3 * wi;
 }
 
 template <int N, int SIGN, typename T>
