@@ -320,39 +320,59 @@ struct OpVjpAssembleHalf {
 
 // loss part of the omega gradient and the final combination:
 // domega[b] = sum_p dlog_p ( dwg[b][p] - (1/N^3) sum_k Re(conj(FG) H) Lam_p(k) ).
-// The spectrum of an item is split into kDomSeg segments of one block each; a
-// block forms x(k) = Re(conj(FG) H)(k) once per point and accumulates x Lam_p
-// for every node p in registers, then reduces each node's sums over the block
-// (wave butterflies, then the four waves in order).
+// The spectrum of an item is split into kDomSeg segments; a block takes one
+// segment of IB items, reads each Lam_p(k) of the segment once for all of them,
+// forms x(k) = Re(conj(FG) H)(k) once per item and point, and accumulates
+// x Lam_p for every node p in registers; then it reduces each sum over the
+// block (wave butterflies, then the four waves in order).  Rows p >= N_rho of
+// the padded width NRM read row N_rho - 1 (no branch in the load stream) and are
+// dropped.  An item's sums do not depend on the other items of its block.
 template <int NRM>
+constexpr int domega_items() {
+  return NRM <= 16 ? 2 : 1;
+}
+
+template <int NRM, int IB = domega_items<NRM>()>
 __global__ __launch_bounds__(256) void k_domega_part(const C<double> *H, const C<double> *FG, const double *lam_p,
-                                                     double *part, int Nr, long n3) {
-  const long b = blockIdx.x / kDomSeg;
+                                                     double *part, long nb, int Nr, long n3) {
+  const long b0 = (blockIdx.x / kDomSeg) * IB;
   const int g = blockIdx.x % kDomSeg;
   const long seg = (n3 + kDomSeg - 1) / kDomSeg;
   const long k0 = g * seg, k1 = (k0 + seg < n3) ? k0 + seg : n3;
-  double acc[NRM];
+  const int ni = (nb - b0 < IB) ? int(nb - b0) : IB;
+  double acc[IB][NRM];
 #pragma unroll
-  for (int q = 0; q < NRM; ++q) acc[q] = 0.0;
+  for (int i = 0; i < IB; ++i)
+#pragma unroll
+    for (int q = 0; q < NRM; ++q) acc[i][q] = 0.0;
   for (long k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
-    const C<double> h = H[b * n3 + k], x = FG[b * n3 + k];
-    const double v = x.re * h.re + x.im * h.im;
+    double lam[NRM];
 #pragma unroll
-    for (int q = 0; q < NRM; ++q)
-      if (q < Nr) acc[q] += v * lam_p[q * n3 + k];
+    for (int q = 0; q < NRM; ++q) lam[q] = lam_p[(q < Nr ? q : Nr - 1) * n3 + k];
+#pragma unroll
+    for (int i = 0; i < IB; ++i) {
+      // items past the batch repeat the last one (valid) and are not written
+      const long b = b0 + (i < ni ? i : ni - 1);
+      const C<double> h = H[b * n3 + k], x = FG[b * n3 + k];
+      const double v = x.re * h.re + x.im * h.im;
+#pragma unroll
+      for (int q = 0; q < NRM; ++q) acc[i][q] += v * lam[q];
+    }
   }
-  __shared__ double red[4][NRM];
+  __shared__ double red[4][IB][NRM];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
 #pragma unroll
-  for (int q = 0; q < NRM; ++q) {
-    double v = acc[q];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if (lane == 0) red[wave][q] = v;
-  }
+  for (int i = 0; i < IB; ++i)
+#pragma unroll
+    for (int q = 0; q < NRM; ++q) {
+      double v = acc[i][q];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      if (lane == 0) red[wave][i][q] = v;
+    }
   __syncthreads();
-  if (int(threadIdx.x) < Nr) {
-    const int q = threadIdx.x;
-    part[blockIdx.x * long(Nr) + q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+  for (int t = threadIdx.x; t < ni * Nr; t += blockDim.x) {
+    const int i = t / Nr, q = t % Nr;
+    part[((b0 + i) * kDomSeg + g) * long(Nr) + q] = ((red[0][i][q] + red[1][i][q]) + red[2][i][q]) + red[3][i][q];
   }
 }
 
@@ -377,14 +397,27 @@ __global__ __launch_bounds__(64) void k_domega_final(const double *part, const d
 static void launch_domega(const C<double> *H, const C<double> *FG, const double *lam_p, const double *dlog,
                           const double *dwg, double *part, double *domega, long nb, int Nr, long n3,
                           hipStream_t st) {
-  const dim3 g(unsigned(nb * kDomSeg)), blk(256);
+  const dim3 blk(256);
+  auto grid = [&](int ib) { return dim3(unsigned((nb + ib - 1) / ib * kDomSeg)); };
   switch (mix_width(Nr)) {
-    case 8: hipLaunchKernelGGL((k_domega_part<8>), g, blk, 0, st, H, FG, lam_p, part, Nr, n3); break;
-    case 16: hipLaunchKernelGGL((k_domega_part<16>), g, blk, 0, st, H, FG, lam_p, part, Nr, n3); break;
-    case 24: hipLaunchKernelGGL((k_domega_part<24>), g, blk, 0, st, H, FG, lam_p, part, Nr, n3); break;
-    case 32: hipLaunchKernelGGL((k_domega_part<32>), g, blk, 0, st, H, FG, lam_p, part, Nr, n3); break;
-    case 48: hipLaunchKernelGGL((k_domega_part<48>), g, blk, 0, st, H, FG, lam_p, part, Nr, n3); break;
-    default: hipLaunchKernelGGL((k_domega_part<64>), g, blk, 0, st, H, FG, lam_p, part, Nr, n3); break;
+    case 8:
+      hipLaunchKernelGGL((k_domega_part<8>), grid(domega_items<8>()), blk, 0, st, H, FG, lam_p, part, nb, Nr, n3);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_domega_part<16>), grid(domega_items<16>()), blk, 0, st, H, FG, lam_p, part, nb, Nr, n3);
+      break;
+    case 24:
+      hipLaunchKernelGGL((k_domega_part<24>), grid(domega_items<24>()), blk, 0, st, H, FG, lam_p, part, nb, Nr, n3);
+      break;
+    case 32:
+      hipLaunchKernelGGL((k_domega_part<32>), grid(domega_items<32>()), blk, 0, st, H, FG, lam_p, part, nb, Nr, n3);
+      break;
+    case 48:
+      hipLaunchKernelGGL((k_domega_part<48>), grid(domega_items<48>()), blk, 0, st, H, FG, lam_p, part, nb, Nr, n3);
+      break;
+    default:
+      hipLaunchKernelGGL((k_domega_part<64>), grid(domega_items<64>()), blk, 0, st, H, FG, lam_p, part, nb, Nr, n3);
+      break;
   }
   hipLaunchKernelGGL(k_domega_final, dim3(unsigned(nb)), dim3(64), 0, st, part, dlog, dwg, domega, Nr, n3);
 }
