@@ -147,14 +147,18 @@ struct OpAdjPencil {
 };
 
 // adjoint accumulation: Z[b] slab k1 = sum_{p,q} c_s(k) * fft2d(Y_(b,p,q) slab k1)
-// over the items [ib0, ib0 + ni) of the sub-chunk; one workgroup owns SPB slabs
-// of Z (possibly of two items) and loops over all N_rho*M tasks of each.  Lane
-// (s, c) owns column c of slab s, as in the generic slab kernel: the column
-// transform runs in registers straight from the coalesced loads, the row
-// transform through LDS, and the accumulators hold the lane's column.
+// over the items [ib0, ib0 + ni) of the sub-chunk.  The N_rho*M tasks (p, q)
+// of a slab are split in two fixed halves (blockIdx.y): the first half's sum
+// goes to Z, the second half's to Zp (sub-chunk relative), and k_adj_acc_add
+// forms Z = first + second, so twice as many workgroups hide the loads' latency
+// while every item's result is the same whatever the chunking.  One workgroup
+// owns SPB slabs of Z (possibly of two items).  Lane (s, c) owns column c of
+// slab s, as in the generic slab kernel: the column transform runs in registers
+// straight from the coalesced loads, the row transform through LDS, and the
+// accumulators hold the lane's column.
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_adj_acc(const C<T> *Y, const C<T> *phase, C<T> *Z, long ib0, long ni,
-                                                 int M, int Nr) {
+__global__ __launch_bounds__(256) void k_adj_acc(const C<T> *Y, const C<T> *phase, C<T> *Z, C<T> *Zp, long ib0,
+                                                 long ni, int M, int Nr) {
   constexpr int SPB = slab_spb2<T, N>();
   constexpr long n2 = long(N) * N, n3 = n2 * N;
   __shared__ T sre[SPB][N][N + 1];
@@ -168,7 +172,9 @@ __global__ __launch_bounds__(256) void k_adj_acc(const C<T> *Y, const C<T> *phas
   T ar[N], ai[N];
   static_for<0, N>([&](auto k) { ar[decltype(k)::value] = T(0); ai[decltype(k)::value] = T(0); });
   const int ntask = Nr * M;
-  for (int task = 0; task < ntask; ++task) {
+  const int half = int(blockIdx.y);
+  const int t0 = (half * ntask) / 2, t1 = ((half + 1) * ntask) / 2;
+  for (int task = t0; task < t1; ++task) {
     const int p = task / M, q = task % M;
     const C<T> *y = Y + ((bl * Nr + p) * M + q) * n3 + long(k1) * n2 + c;
     T xr[N], xi[N];
@@ -207,9 +213,18 @@ __global__ __launch_bounds__(256) void k_adj_acc(const C<T> *Y, const C<T> *phas
     __syncthreads();
   }
   if (z < nz) {
-    C<T> *zo = Z + (ib0 + bl) * n3 + long(k1) * n2 + c;
+    C<T> *zo = (half == 0 ? Z + (ib0 + bl) * n3 : Zp + bl * n3) + long(k1) * n2 + c;
     static_for<0, N>([&](auto r) { zo[decltype(r)::value * N] = C<T>{ar[decltype(r)::value], ai[decltype(r)::value]}; });
   }
+}
+
+// Z[ib0 + i] += Zp[i] for the ni items of a sub-chunk (n complex values each)
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_acc_add(C<T> *Z, const C<T> *Zp, long n) {
+  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const C<T> a = Z[i], b = Zp[i];
+  Z[i] = C<T>{a.re + b.re, a.im + b.im};
 }
 
 // loss adjoint spectrum, FP64: Lam (H + i FG), slab = item*N + k1
@@ -588,8 +603,11 @@ struct Vjp {
           OpAdjPencil<T, N> op{Y, Hp, reinterpret_cast<const T *>(p.wq), domega ? dwg : nullptr, bp0, M};
           if ((s = P::pencil(op, cnt * N * N, st, "vjp gain pencil"))) return s;
           TimedLaunch tl("vjp gain acc", st);
-          hipLaunchKernelGGL((k_adj_acc<T, N>), dim3(nblk(ni * N, SPB)), dim3(SPB * N), 0, st, Y,
-                             reinterpret_cast<const C<T> *>(p.phase), Z, ib0, ni, M, Nr);
+          // second half of the tasks into GT (the spectrum of g is no longer needed)
+          hipLaunchKernelGGL((k_adj_acc<T, N>), dim3(nblk(ni * N, SPB), 2), dim3(SPB * N), 0, st, Y,
+                             reinterpret_cast<const C<T> *>(p.phase), Z, GT, ib0, ni, M, Nr);
+          hipLaunchKernelGGL((k_adj_acc_add<T>), dim3(nblk(ni * n3, 256)), dim3(256), 0, st, Z + ib0 * n3, GT,
+                             ni * n3);
           QC_LAUNCH_CHECK("vjp gain acc");
         }
         // gain inverse (slab pass; the pencil pass is in the assembly)
