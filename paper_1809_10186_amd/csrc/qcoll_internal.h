@@ -97,6 +97,9 @@ inline bool onchip_schedule_supported(int N, int precision) {
 void launch_sum_nodes(const void *W, void *out, long nitems, int Nr, long n_in, long n_out, hipStream_t st);
 // fused gain adjoint of the VJP (FP32, N <= 32, VHS kernels)
 bool use_fused_adjoint(const Plan &p);
+// two-pass VJP: the largest item count whose adjoint accumulation launch fits
+// the device's resident workgroups in one round (0 if the query fails)
+long adj_acc_items_per_round(const Plan &p);
 qcoll_status launch_adjoint_fused(const Plan &p, const void *H, const float *Hp, void *Zh, double *dwg, long nbp,
                                   hipStream_t st);
 

@@ -780,13 +780,22 @@ Layout make_layout(const Plan &p, int64_t batch, int op) {
   size_t o = 0;
   if (op == 1) {
     // vjp: items per chunk and per gain sub-chunk (Y holds N_rho*M complex volumes per item).
-    // The adjoint accumulation runs one workgroup per slab pair of the sub-chunk's
-    // items, so the sub-chunk must hold enough items to fill the GPU (32 items at
-    // N = 32: 512 workgroups); Y is capped at 4 GiB.
+    // The two-pass adjoint accumulation runs two workgroups (task halves) per
+    // group of slabs of the sub-chunk's items, so the sub-chunk must hold enough
+    // items to fill the GPU (32 items at N = 32 in FP64: 1024 workgroups); Y is
+    // capped at 4 GiB.
     l.bc = batch < 32 ? (batch > 0 ? batch : 1) : 32;
     const size_t per_item_y = size_t(p.N_rho) * p.M * n3 * 2 * es;
     long pc = long((size_t(4) << 30) / per_item_y);
     l.pc = pc < 1 ? 1 : (pc > l.bc ? l.bc : pc);
+    if (!use_fused_adjoint(p)) {
+      // sub-chunks that fill the accumulation kernel's resident workgroups in
+      // whole rounds, and chunks of whole sub-chunks (no small tail launch per
+      // chunk); the chunking does not change any item's result
+      const long round = adj_acc_items_per_round(p);
+      if (round >= 1 && round < l.pc) l.pc = round * (l.pc / round);
+      if (l.pc < l.bc) l.bc = l.pc * (l.bc / l.pc);
+    }
     const size_t c64 = size_t(l.bc) * n3 * 2 * sizeof(double), cT = size_t(l.bc) * n3 * 2 * es;
     l.off_h64 = o; o += al(c64);
     l.off_g = o; o += al(c64);

@@ -637,6 +637,41 @@ struct Vjp {
   }
 };
 
+template <typename T, int N>
+static long adj_acc_round(int cus) {
+  constexpr int SPB = slab_spb2<T, N>();
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(&k_adj_acc<T, N>), SPB * N,
+                                                   0) != hipSuccess)
+    return 0;
+  // the launch for ni items has 2 * ceil(ni N / SPB) workgroups (two task halves)
+  const long slots = long(occ) * cus;
+  long ni = 0;
+  while (2 * ((long(ni + 1) * N + SPB - 1) / SPB) <= slots) ++ni;
+  return ni;
+}
+
+template <typename T>
+static long adj_acc_round_t(int N, int cus) {
+  switch (N) {
+    case 8: return adj_acc_round<T, 8>(cus);
+    case 12: return adj_acc_round<T, 12>(cus);
+    case 16: return adj_acc_round<T, 16>(cus);
+    case 24: return adj_acc_round<T, 24>(cus);
+    case 32: return adj_acc_round<T, 32>(cus);
+    case 48: return adj_acc_round<T, 48>(cus);
+    default: return 0;
+  }
+}
+
+long adj_acc_items_per_round(const Plan &p) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    return 0;
+  return p.precision == QCOLL_FP32 ? adj_acc_round_t<float>(p.N, cus) : adj_acc_round_t<double>(p.N, cus);
+}
+
 template <typename T>
 static qcoll_status vjp_dispatch(const Plan &p, int64_t batch, const double *f, const double *g, double *df,
                                  double *domega, bool through, void *ws, const Layout &lay, hipStream_t st) {
