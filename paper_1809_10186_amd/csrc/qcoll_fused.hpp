@@ -33,6 +33,10 @@ struct FusedGeom {
   // (64 lanes = 64/N rows of N lanes, one pencil per lane)
   static constexpr bool WAVE_BC = (PPL == 1) && (64 % N == 0);
   static constexpr size_t lds_bytes = size_t(N) * S1 * sizeof(float);
+  // waves per SIMD the register budget must allow: at N = 24 a workgroup is 9
+  // waves with a 57 KiB tile, and 5 waves per SIMD let two workgroups share a
+  // CU (their barrier phases then overlap); elsewhere no constraint
+  static constexpr int WPE = (N == 24) ? 5 : 1;
 };
 
 // move one component (re or im) of every pencil of the lane through LDS; with

@@ -35,7 +35,7 @@ namespace qcoll {
 // half spectrum (planes k1 <= N/2) in registers; the weights carry w_p w_q,
 // so the multiplier is not scaled by sqrt(w_q).  The epilogue stores that sum.
 template <int N, bool VSS>
-__global__ __launch_bounds__(FusedGeom<N>::NL) void k_gain_fused(const cplx<float> *__restrict__ H,
+__global__ __launch_bounds__(FusedGeom<N>::NL, FusedGeom<N>::WPE) void k_gain_fused(const cplx<float> *__restrict__ H,
                                                                  const cplx<float> *__restrict__ phase,
                                                                  const float *__restrict__ wq,
                                                                  const float *__restrict__ alpha_eff,
