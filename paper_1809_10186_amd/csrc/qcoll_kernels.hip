@@ -815,6 +815,7 @@ Layout make_layout(const Plan &p, int64_t batch, int op) {
     l.off_d = o; o += al(size_t(l.bc) * p.N_rho * sizeof(double));
     l.off_pm = o; o += al(size_t(l.bc) * kProjSeg * 5 * sizeof(double));
     l.off_dp = o; o += al(size_t(l.bc) * kDomSeg * p.N_rho * sizeof(double));
+    l.off_pd = o; o += use_fused_adjoint(p) ? 0 : al(size_t(l.bc) * p.N_rho * p.N * p.N * sizeof(double));
     l.total = o;
     return l;
   }

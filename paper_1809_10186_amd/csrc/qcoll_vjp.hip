@@ -104,14 +104,15 @@ static void launch_unpack_mix(const C<T> *R, const T *U, T *Hp, long nitems, int
 }
 
 // adjoint pencil pass: per (item, p) pair and pencil (j2, j3), for every q:
-// u = inverse along axis 1; y = w_q h_p conj(u); <h_p, w_q t1 t2> accumulated;
-// y transformed forward along axis 1 and stored back in place.
+// u = inverse along axis 1; y = w_q h_p conj(u); the pencil's part of
+// <h_p, sum_q w_q t1 t2> is stored per pencil (summed per pair in a fixed order
+// by k_pair_dot_sum); y transformed forward along axis 1 and stored back in place.
 template <typename T, int N>
 struct OpAdjPencil {
   C<T> *Y;
   const T *Hp;
   const T *wq;
-  double *dwg;     // [pairs] accumulators of <h_p, A_p>, or null
+  double *dots;    // [pairs][N^2] per-pencil parts of <h_p, A_p>, or null
   long bp0;        // first (item, p) pair of this launch (within the chunk)
   int M;
   __device__ void operator()(long bpl, int r) const {
@@ -142,9 +143,23 @@ struct OpAdjPencil {
       fft_reg<N, -1, T>(xr, xi);
       static_for<0, N>([&](auto k) { y[decltype(k)::value * n2] = C<T>{xr[decltype(k)::value], xi[decltype(k)::value]}; });
     }
-    if (dwg) atomicAdd(dwg + bp0 + bpl, dot);
+    if (dots) dots[(bp0 + bpl) * n2 + r] = dot;
   }
 };
+
+// dwg[pair] = sum of the pair's n per-pencil parts, in a fixed order (strided
+// per-thread sums, wave butterflies, then the four waves in order)
+__global__ __launch_bounds__(256) void k_pair_dot_sum(const double *dots, double *dwg, long n) {
+  const long bp = blockIdx.x;
+  double v = 0.0;
+  for (long i = threadIdx.x; i < n; i += blockDim.x) v += dots[bp * n + i];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  __shared__ double red[4];
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) dwg[bp] = ((red[0] + red[1]) + red[2]) + red[3];
+}
 
 // adjoint accumulation: Z[b] slab k1 = sum_{p,q} c_s(k) * fft2d(Y_(b,p,q) slab k1)
 // over the items [ib0, ib0 + ni) of the sub-chunk.  The N_rho*M tasks (p, q)
@@ -536,6 +551,7 @@ struct Vjp {
     double *dwg = reinterpret_cast<double *>(w + lay.off_d);
     double *pm = reinterpret_cast<double *>(w + lay.off_pm);
     double *dpart = reinterpret_cast<double *>(w + lay.off_dp);
+    double *pdots = reinterpret_cast<double *>(w + lay.off_pd);
     const int S = p.nv, np = p.npair(), Nr = p.N_rho, M = p.M;
     const bool fused_adjoint = std::is_same<T, float>::value && use_fused_adjoint(p);
     qcoll_status s;
@@ -600,7 +616,7 @@ struct Vjp {
           if ((s = P::template slab<SrcShift<T, N>, DstCplx<T, N>, +1>(src, DstCplx<T, N>{Y}, cnt * M * N, st,
                                                                         "vjp gain slab")))
             return s;
-          OpAdjPencil<T, N> op{Y, Hp, reinterpret_cast<const T *>(p.wq), domega ? dwg : nullptr, bp0, M};
+          OpAdjPencil<T, N> op{Y, Hp, reinterpret_cast<const T *>(p.wq), domega ? pdots : nullptr, bp0, M};
           if ((s = P::pencil(op, cnt * N * N, st, "vjp gain pencil"))) return s;
           TimedLaunch tl("vjp gain acc", st);
           // second half of the tasks into GT (the spectrum of g is no longer needed)
@@ -609,6 +625,10 @@ struct Vjp {
           hipLaunchKernelGGL((k_adj_acc_add<T>), dim3(nblk(ni * n3, 256)), dim3(256), 0, st, Z + ib0 * n3, GT,
                              ni * n3);
           QC_LAUNCH_CHECK("vjp gain acc");
+        }
+        if (domega) {
+          hipLaunchKernelGGL(k_pair_dot_sum, dim3(unsigned(nb * Nr)), dim3(256), 0, st, pdots, dwg, long(N) * N);
+          QC_LAUNCH_CHECK("vjp pair dots");
         }
         // gain inverse (slab pass; the pencil pass is in the assembly)
         if ((s = P::template slab<SrcCplx<T, N>, DstCplx<T, N>, +1>(SrcCplx<T, N>{Z}, DstCplx<T, N>{Z}, nb * N, st,

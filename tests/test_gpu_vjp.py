@@ -227,3 +227,23 @@ def test_many_radial_nodes_eval_and_vjp(N_rho):
         assert e <= tol and et <= tol
         assert ed <= TOL[prec]
         assert ew <= (1e-10 if prec == qc.QCOLL_FP64 else 1e-4)
+
+
+@pytest.mark.parametrize("precision,N,L", [(qc.QCOLL_FP64, 16, 6.0), (qc.QCOLL_FP64, 32, 6.0),
+                                           (qc.QCOLL_FP32, 48, 9.0)])
+def test_two_pass_vjp_independent_of_chunking(precision, N, L):
+    """Every item's df and d omega from the two-pass adjoint are the same bit for
+    bit whether it is processed alone or inside a batch of several chunks and
+    sub-chunks (the accumulation's fixed task halves, the sub-chunk sizing)."""
+    batch = {16: 40, 32: 36, 48: 23}[N]
+    print(f"case two-pass vjp chunking N={N} prec={precision} batch={batch}", flush=True)
+    sph = W.sphere_rule(12)
+    f = W.maxwellian_mixture(batch, N, L, 900 + N)
+    g = W.cotangent(f, 901 + N)
+    plan = qc.Plan(N, L, 16, sphere=sph, omega=0.81, precision=precision)
+    df, dw = plan.vjp(gpu(f), gpu(g), through_conserve=True, want_domega=True)
+    for lo, hi in ((0, 1), (batch - 3, batch)):
+        d1, w1 = plan.vjp(gpu(f[lo:hi]), gpu(g[lo:hi]), through_conserve=True, want_domega=True)
+        assert torch.equal(d1, df[lo:hi])
+        assert torch.equal(w1, dw[lo:hi])
+    plan.close()
