@@ -188,10 +188,12 @@ struct SrcShift {
     const long b = bp / Nr;
     const int p = int(bp % Nr);
     const C<T> *ph = phase + size_t(p * M + q) * 3 * N;
+    // m = Re(b1 b2 b3) + Im(b1 b2 b3) = b2.re P + b2.im Q with P, Q from b1 b3,
+    // which do not depend on the row r (computed once per lane and column)
     const C<T> b1 = ph[k1], b2 = ph[N + r], b3 = ph[2 * N + c];
-    const T x12 = b1.re * b2.re - b1.im * b2.im, y12 = b1.re * b2.im + b1.im * b2.re;
-    const T x = x12 * b3.re - y12 * b3.im, y = x12 * b3.im + y12 * b3.re;
-    const T m = (x + y) * scale;
+    const T x13 = b1.re * b3.re - b1.im * b3.im, y13 = b1.re * b3.im + b1.im * b3.re;
+    const T P = (x13 + y13) * scale, Q = (x13 - y13) * scale;
+    const T m = b2.re * P + b2.im * Q;
     const C<T> h = H[((b * N + k1) * N + r) * N + c];
     return C<T>{h.re * m, h.im * m};
   }

@@ -218,10 +218,12 @@ __global__ __launch_bounds__(256) void k_adj_acc(const C<T> *Y, const C<T> *phas
     const C<T> *ph = phase + size_t(p * M + q) * 3 * N;
     const C<T> b1 = ph[k1], b3 = ph[2 * N + c];
     const T x13 = b1.re * b3.re - b1.im * b3.im, y13 = b1.re * b3.im + b1.im * b3.re;
+    // c_s = Re(b13 b2) + Im(b13 b2) = b2.re P + b2.im Q
+    const T P = x13 + y13, Q = x13 - y13;
     static_for<0, N>([&](auto r) {
       constexpr int rr = decltype(r)::value;
       const C<T> b2 = ph[N + rr];
-      const T cm = (x13 * b2.re - y13 * b2.im) + (x13 * b2.im + y13 * b2.re);
+      const T cm = b2.re * P + b2.im * Q;
       ar[rr] += cm * sre[s][rr][c];
       ai[rr] += cm * sim[s][rr][c];
     });
@@ -522,11 +524,6 @@ __global__ __launch_bounds__(256) void k_project_apply(const double *in, double 
   }
 }
 
-__global__ void k_fill(double *p, long n, double v) {
-  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
 template <typename T, int N>
 struct Vjp {
   using P = Passes<T, N>;
@@ -584,10 +581,6 @@ struct Vjp {
         TimedLaunch tl("vjp unpack", st);
         launch_unpack_mix<T>(R, reinterpret_cast<const T *>(p.umix_d), Hp, nb, S, Nr, np, n3, st);
         QC_LAUNCH_CHECK("vjp unpack");
-      }
-      if (domega) {
-        hipLaunchKernelGGL(k_fill, dim3(nblk(nb * Nr, 256)), dim3(256), 0, st, dwg, nb * Nr, 0.0);
-        QC_LAUNCH_CHECK("fill");
       }
       if (fused_adjoint) {
         // gain adjoint on chip, one workgroup per (item, p) pair, then the sum
