@@ -387,12 +387,18 @@ struct OpGainVss {
 };
 
 // Slab accumulation: W[pair] plane k1 (<= N/2) = sum_q alpha_pq(k) fft2(Y[(pair, q)] plane k1)
-// over the (j2, j3) axes.  One workgroup owns SPB planes; lane (s, c) owns column c
-// of plane s (as in the generic slab kernel: column transform from the coalesced
+// over the (j2, j3) axes.  The M terms of a plane are split in kVssParts fixed
+// parts (blockIdx.y): part 0's sum goes to W, part i's to Wp[i - 1] (launch
+// relative), and k_vss_acc_add forms ((part 0 + part 1) + ...), so several
+// workgroups share a plane's loads while every pair's result is independent of
+// the launch sizes.  One workgroup owns SPB planes; lane (s, c) owns column c of
+// plane s (as in the generic slab kernel: column transform from the coalesced
 // loads, row transform through LDS) and keeps that column's sums in registers.
+constexpr int kVssParts = 4;
+
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_vss_acc(const C<T> *Y, const T *apq, C<T> *W, long bp0, long npair, int M,
-                                                 int Nr) {
+__global__ __launch_bounds__(256) void k_vss_acc(const C<T> *Y, const T *apq, C<T> *W, C<T> *Wp, long bp0,
+                                                 long npair, int M, int Nr) {
   constexpr int SPB = slab_spb2<T, N>();
   constexpr int H1 = N / 2 + 1;
   constexpr long n2 = long(N) * N, n3 = n2 * N, nh = long(H1) * n2;
@@ -407,7 +413,9 @@ __global__ __launch_bounds__(256) void k_vss_acc(const C<T> *Y, const T *apq, C<
   const int p = int((bp0 + pl) % Nr);
   T ar[N], ai[N];
   static_for<0, N>([&](auto k) { ar[decltype(k)::value] = T(0); ai[decltype(k)::value] = T(0); });
-  for (int q = 0; q < M; ++q) {
+  const int part = int(blockIdx.y);
+  const int q0 = (part * M) / kVssParts, q1 = ((part + 1) * M) / kVssParts;
+  for (int q = q0; q < q1; ++q) {
     const C<T> *y = Y + (pl * M + q) * n3 + long(k1) * n2 + c;
     T xr[N], xi[N];
     static_for<0, N>([&](auto r) {
@@ -442,9 +450,24 @@ __global__ __launch_bounds__(256) void k_vss_acc(const C<T> *Y, const T *apq, C<
     __syncthreads();
   }
   if (z < nz) {
-    C<T> *wo = W + pl * nh + long(k1) * n2 + c;
+    C<T> *wo = (part == 0 ? W : Wp + (part - 1) * npair * nh) + pl * nh + long(k1) * n2 + c;
     static_for<0, N>([&](auto r) { wo[decltype(r)::value * N] = C<T>{ar[decltype(r)::value], ai[decltype(r)::value]}; });
   }
+}
+
+// W[i] = ((W[i] + Wp[0][i]) + Wp[1][i]) + ... for the n values of a launch
+template <typename T>
+__global__ __launch_bounds__(256) void k_vss_acc_add(C<T> *W, const C<T> *Wp, long n) {
+  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  C<T> a = W[i];
+#pragma unroll
+  for (int k = 0; k < kVssParts - 1; ++k) {
+    const C<T> b = Wp[k * n + i];
+    a.re += b.re;
+    a.im += b.im;
+  }
+  W[i] = a;
 }
 
 // ----------------------------------------------------------------------------
@@ -506,7 +529,8 @@ struct Engine {
   // accumulation over q into the pair's half spectrum W; then the node sum and
   // the half-spectrum tail of the fused schedule.
   static qcoll_status eval_vss(const Plan &p, const C<T> *H, const C<double> *H64, T *A, C<T> *Y, C<T> *TA,
-                               C<double> *LH, const double *fb, double *Qb, long nb, long pc, hipStream_t st) {
+                               C<T> *VP, C<double> *LH, const double *fb, double *Qb, long nb, long pc,
+                               hipStream_t st) {
     constexpr int H1 = N / 2 + 1;
     constexpr long nh = long(H1) * N * N;
     constexpr int SPB = slab_spb2<T, N>();
@@ -524,8 +548,10 @@ struct Engine {
         return s;
       if ((s = pencil(OpGainVss<T, N>{Y, p.M}, cnt * p.M * N * N, st, "vss pencil"))) return s;
       TimedLaunch tl("vss acc", st);
-      hipLaunchKernelGGL((k_vss_acc<T, N>), dim3(nblk(cnt * H1, SPB)), dim3(SPB * N), 0, st, Y,
-                         reinterpret_cast<const T *>(p.alpha_pq), Wp + bp0 * nh, bp0, cnt, p.M, p.N_rho);
+      hipLaunchKernelGGL((k_vss_acc<T, N>), dim3(nblk(cnt * H1, SPB), kVssParts), dim3(SPB * N), 0, st, Y,
+                         reinterpret_cast<const T *>(p.alpha_pq), Wp + bp0 * nh, VP, bp0, cnt, p.M, p.N_rho);
+      hipLaunchKernelGGL((k_vss_acc_add<T>), dim3(nblk(cnt * nh, 256)), dim3(256), 0, st, Wp + bp0 * nh, VP,
+                         cnt * nh);
       QC_LAUNCH_CHECK("vss acc");
     }
     {
@@ -566,6 +592,7 @@ struct Engine {
     C<T> *TA = reinterpret_cast<C<T> *>(w + lay.off_t);
     C<double> *LH = reinterpret_cast<C<double> *>(w + lay.off_l);
     C<T> *Y = reinterpret_cast<C<T> *>(w + lay.off_y);
+    C<T> *VP = reinterpret_cast<C<T> *>(w + lay.off_vp);
     const int S = p.nv, np = p.npair();
     for (long b0 = 0; b0 < batch; b0 += lay.bc) {
       const long nb = (batch - b0 < lay.bc) ? (batch - b0) : lay.bc;
@@ -579,7 +606,7 @@ struct Engine {
         if ((s = Passes<double, N>::forward(fb, H64, nb, st))) return s;
       }
       if (p.is_vss()) {
-        if ((s = eval_vss(p, H, H64, A, Y, TA, LH, fb, Q + b0 * n3, nb, lay.pc, st))) return s;
+        if ((s = eval_vss(p, H, H64, A, Y, TA, VP, LH, fb, Q + b0 * n3, nb, lay.pc, st))) return s;
         continue;
       }
       if (g) {
@@ -847,6 +874,9 @@ Layout make_layout(const Plan &p, int64_t batch, int op) {
   l.off_l = o; o += al(size_t(l.bc) * n3 * 2 * sizeof(double));
   const bool q64 = use_gain_q64(p) && !bil;   // FP64 gain on chip: no per-term volumes
   l.off_y = o; o += (fused || q64) ? 0 : al(size_t(l.pc) * p.M * n3 * 2 * es);
+  // two-pass VSS: the partial half spectra of the accumulation's parts 1.. of a launch
+  l.off_vp = o;
+  o += (vss && !fused && !bil) ? al(size_t(kVssParts - 1) * l.pc * (p.N / 2 + 1) * p.N * p.N * 2 * es) : 0;
   if (bil) {
     l.off_hg = o; o += al(size_t(l.bc) * n3 * 2 * es);
     l.off_h64g = o; o += al(size_t(l.bc) * n3 * 2 * sizeof(double));
