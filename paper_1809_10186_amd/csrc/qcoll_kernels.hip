@@ -17,6 +17,18 @@ namespace qcoll {
 // hot loop, pencil pass: for each (b, p) and pencil (j2, j3), inverse
 // transform along the first axis for every q and accumulate
 // A_p += w_q (u_re^2 - u_im^2)  (= w_q t1 t2 with t1 = re - im, t2 = re + im).
+// For FP64 at 32^3 (32 pairs per launch: two waves per CU otherwise) the M
+// terms of a pencil are split in four fixed parts held by four adjacent lanes
+// (launch index = 4 * (pair * N^2 + pencil) + part); the quad adds its sums as
+// (part 0 + part 1) + (part 2 + part 3) and part 0 stores, so four times the
+// lanes share the loads while every pair's result is independent of the launch
+// sizes.  Elsewhere the four loads of a quad touch four term volumes instead of
+// one run of pencils, which measured slower (FP32 48^3, FP64 24^3).
+template <typename T, int N>
+constexpr int acc_parts() {
+  return (std::is_same<T, double>::value && N == 32) ? 4 : 1;
+}
+
 template <typename T, int N>
 struct OpGainAcc {
   const C<T> *Y;
@@ -24,11 +36,19 @@ struct OpGainAcc {
   T *A;
   long bp0;
   int M;
-  __device__ void operator()(long bpl, int r) const {
+  // called as (g / N^2, g % N^2) for the launch index g
+  __device__ void operator()(long v, int rr) const {
     constexpr long n2 = long(N) * N, n3 = n2 * N;
+    constexpr int P = acc_parts<T, N>();
+    const long g = v * n2 + rr;
+    const int part = int(g % P);
+    const long pen = g / P;
+    const long bpl = pen / n2;
+    const int r = int(pen % n2);
     T acc[N];
     static_for<0, N>([&](auto j) { acc[decltype(j)::value] = T(0); });
-    for (int q = 0; q < M; ++q) {
+    const int q0 = (part * M) / P, q1 = ((part + 1) * M) / P;
+    for (int q = q0; q < q1; ++q) {
       const C<T> *y = Y + (bpl * M + q) * n3 + r;
       T xr[N], xi[N];
       static_for<0, N>([&](auto k) {
@@ -43,8 +63,19 @@ struct OpGainAcc {
         acc[jj] += w * (xr[jj] * xr[jj] - xi[jj] * xi[jj]);
       });
     }
-    T *a = A + (bp0 + bpl) * n3 + r;
-    static_for<0, N>([&](auto j) { a[decltype(j)::value * n2] = acc[decltype(j)::value]; });
+    if constexpr (P == 4) {
+      // (a0 + a1) + (a2 + a3) in every lane of the quad (all four lanes are
+      // active: launches hold whole quads)
+      static_for<0, N>([&](auto j) {
+        constexpr int jj = decltype(j)::value;
+        acc[jj] += __shfl_xor(acc[jj], 1);
+        acc[jj] += __shfl_xor(acc[jj], 2);
+      });
+    }
+    if (part == 0) {
+      T *a = A + (bp0 + bpl) * n3 + r;
+      static_for<0, N>([&](auto j) { a[decltype(j)::value * n2] = acc[decltype(j)::value]; });
+    }
   }
 };
 
@@ -499,7 +530,7 @@ struct Engine {
       if ((s = slab<SrcShift<T, N>, DstCplx<T, N>, +1>(src, DstCplx<T, N>{Y}, cnt * p.M * N, st, "gain slab")))
         return s;
       OpGainAcc<T, N> op{Y, reinterpret_cast<const T *>(p.wq), A, bp0, p.M};
-      if ((s = pencil(op, cnt * N * N, st, "gain pencil"))) return s;
+      if ((s = pencil(op, cnt * acc_parts<T, N>() * N * N, st, "gain pencil"))) return s;
     }
     return QCOLL_OK;
   }
