@@ -17,18 +17,6 @@ namespace qcoll {
 // hot loop, pencil pass: for each (b, p) and pencil (j2, j3), inverse
 // transform along the first axis for every q and accumulate
 // A_p += w_q (u_re^2 - u_im^2)  (= w_q t1 t2 with t1 = re - im, t2 = re + im).
-// For FP64 at 32^3 (32 pairs per launch: two waves per CU otherwise) the M
-// terms of a pencil are split in four fixed parts held by four adjacent lanes
-// (launch index = 4 * (pair * N^2 + pencil) + part); the quad adds its sums as
-// (part 0 + part 1) + (part 2 + part 3) and part 0 stores, so four times the
-// lanes share the loads while every pair's result is independent of the launch
-// sizes.  Elsewhere the four loads of a quad touch four term volumes instead of
-// one run of pencils, which measured slower (FP32 48^3, FP64 24^3).
-template <typename T, int N>
-constexpr int acc_parts() {
-  return (std::is_same<T, double>::value && N == 32) ? 4 : 1;
-}
-
 template <typename T, int N>
 struct OpGainAcc {
   const C<T> *Y;
@@ -36,19 +24,11 @@ struct OpGainAcc {
   T *A;
   long bp0;
   int M;
-  // called as (g / N^2, g % N^2) for the launch index g
-  __device__ void operator()(long v, int rr) const {
+  __device__ void operator()(long bpl, int r) const {
     constexpr long n2 = long(N) * N, n3 = n2 * N;
-    constexpr int P = acc_parts<T, N>();
-    const long g = v * n2 + rr;
-    const int part = int(g % P);
-    const long pen = g / P;
-    const long bpl = pen / n2;
-    const int r = int(pen % n2);
     T acc[N];
     static_for<0, N>([&](auto j) { acc[decltype(j)::value] = T(0); });
-    const int q0 = (part * M) / P, q1 = ((part + 1) * M) / P;
-    for (int q = q0; q < q1; ++q) {
+    for (int q = 0; q < M; ++q) {
       const C<T> *y = Y + (bpl * M + q) * n3 + r;
       T xr[N], xi[N];
       static_for<0, N>([&](auto k) {
@@ -63,21 +43,63 @@ struct OpGainAcc {
         acc[jj] += w * (xr[jj] * xr[jj] - xi[jj] * xi[jj]);
       });
     }
-    if constexpr (P == 4) {
-      // (a0 + a1) + (a2 + a3) in every lane of the quad (all four lanes are
-      // active: launches hold whole quads)
-      static_for<0, N>([&](auto j) {
-        constexpr int jj = decltype(j)::value;
-        acc[jj] += __shfl_xor(acc[jj], 1);
-        acc[jj] += __shfl_xor(acc[jj], 2);
-      });
-    }
-    if (part == 0) {
-      T *a = A + (bp0 + bpl) * n3 + r;
-      static_for<0, N>([&](auto j) { a[decltype(j)::value * n2] = acc[decltype(j)::value]; });
-    }
+    T *a = A + (bp0 + bpl) * n3 + r;
+    static_for<0, N>([&](auto j) { a[decltype(j)::value * n2] = acc[decltype(j)::value]; });
   }
 };
+
+// The same pencil pass with the M terms of each pencil split in kGainParts
+// fixed parts, one wave per part: a workgroup owns 64 consecutive pencils (so
+// every wave's loads stay one coalesced run), waves 1.. leave their sums in
+// LDS and wave 0 adds them in order, ((part 0 + part 1) + ...), and stores.
+// A launch of 32 pairs at 32^3 (or 18 at 48^3) otherwise runs about two waves
+// per CU.  The split is fixed by M, so a pair's result does not depend on the
+// launch sizes.  Needs N^2 to be a multiple of 64 and the parts' sums to fit
+// 48 KiB of LDS (not FP64 at 48^3).
+constexpr int kGainParts = 4;
+
+template <typename T, int N>
+__global__ __launch_bounds__(64 * kGainParts) void k_gain_pencil_parts(const C<T> *Y, const T *wq, T *A, long bp0,
+                                                                       int M) {
+  constexpr long n2 = long(N) * N, n3 = n2 * N;
+  __shared__ T part_acc[kGainParts - 1][N][64];
+  const int lane = int(threadIdx.x) % 64, part = int(threadIdx.x) / 64;
+  const long pen = long(blockIdx.x) * 64 + lane;   // the grid covers whole groups of 64 pencils
+  const long bpl = pen / n2;
+  const int r = int(pen % n2);
+  T acc[N];
+  static_for<0, N>([&](auto j) { acc[decltype(j)::value] = T(0); });
+  const int q0 = (part * M) / kGainParts, q1 = ((part + 1) * M) / kGainParts;
+  for (int q = q0; q < q1; ++q) {
+    const C<T> *y = Y + (bpl * M + q) * n3 + r;
+    T xr[N], xi[N];
+    static_for<0, N>([&](auto k) {
+      const C<T> v = y[decltype(k)::value * n2];
+      xr[decltype(k)::value] = v.re;
+      xi[decltype(k)::value] = v.im;
+    });
+    fft_reg<N, +1, T>(xr, xi);
+    const T w = wq[q];
+    static_for<0, N>([&](auto j) {
+      constexpr int jj = decltype(j)::value;
+      acc[jj] += w * (xr[jj] * xr[jj] - xi[jj] * xi[jj]);
+    });
+  }
+  if (part > 0) static_for<0, N>([&](auto j) { part_acc[part - 1][decltype(j)::value][lane] = acc[decltype(j)::value]; });
+  __syncthreads();
+  if (part == 0) {
+#pragma unroll
+    for (int k = 0; k < kGainParts - 1; ++k)
+      static_for<0, N>([&](auto j) { acc[decltype(j)::value] += part_acc[k][decltype(j)::value][lane]; });
+    T *a = A + (bp0 + bpl) * n3 + r;
+    static_for<0, N>([&](auto j) { a[decltype(j)::value * n2] = acc[decltype(j)::value]; });
+  }
+}
+
+template <typename T, int N>
+constexpr bool gain_pencil_parts() {
+  return (long(N) * N) % 64 == 0 && size_t(kGainParts - 1) * N * 64 * sizeof(T) <= 48 * 1024;
+}
 
 // bilinear hot loop, pencil pass: u_f and u_g inverse along axis 1 for every
 // q; A_p += w_q Re(u_f u_g)  (= w_q (t1_f t2_g + t2_f t1_g) / 2)
@@ -529,8 +551,15 @@ struct Engine {
       qcoll_status s;
       if ((s = slab<SrcShift<T, N>, DstCplx<T, N>, +1>(src, DstCplx<T, N>{Y}, cnt * p.M * N, st, "gain slab")))
         return s;
-      OpGainAcc<T, N> op{Y, reinterpret_cast<const T *>(p.wq), A, bp0, p.M};
-      if ((s = pencil(op, cnt * acc_parts<T, N>() * N * N, st, "gain pencil"))) return s;
+      if constexpr (gain_pencil_parts<T, N>()) {
+        TimedLaunch tl("gain pencil", st);
+        hipLaunchKernelGGL((k_gain_pencil_parts<T, N>), dim3(unsigned(cnt * N * N / 64)), dim3(64 * kGainParts), 0,
+                           st, Y, reinterpret_cast<const T *>(p.wq), A, bp0, p.M);
+        QC_LAUNCH_CHECK("gain pencil");
+      } else {
+        OpGainAcc<T, N> op{Y, reinterpret_cast<const T *>(p.wq), A, bp0, p.M};
+        if ((s = pencil(op, cnt * N * N, st, "gain pencil"))) return s;
+      }
     }
     return QCOLL_OK;
   }
