@@ -171,9 +171,16 @@ __global__ __launch_bounds__(256) void k_pair_dot_sum(const double *dots, double
 // slab s, as in the generic slab kernel: the column transform runs in registers
 // straight from the coalesced loads, the row transform through LDS, and the
 // accumulators hold the lane's column.
+// waves per SIMD the register budget must allow: at 48^3 in FP32 a one-wave
+// workgroup needs 18.8 KiB of LDS, so eight fit a CU once the registers do
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_adj_acc(const C<T> *Y, const C<T> *phase, C<T> *Z, C<T> *Zp, long ib0,
-                                                 long ni, int M, int Nr) {
+constexpr int adj_acc_wpe() {
+  return (std::is_same<T, float>::value && N == 48) ? 2 : 1;
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256, (adj_acc_wpe<T, N>())) void k_adj_acc(const C<T> *Y, const C<T> *phase, C<T> *Z,
+                                                                      C<T> *Zp, long ib0, long ni, int M, int Nr) {
   constexpr int SPB = slab_spb2<T, N>();
   constexpr long n2 = long(N) * N, n3 = n2 * N;
   __shared__ T sre[SPB][N][N + 1];
