@@ -180,7 +180,9 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_adj_fused(const cplx<float
   cplx<float> *zo = Zh + bp * (long(H1) * n2);
   static_for<0, H1>([&](auto s) {
     constexpr int ss = decltype(s)::value;
-    zo[ss * n2 + lane] = cplx<float>{acc[2 * ss], acc[2 * ss + 1]};
+    // streaming store: read once, by the node sum; keeps the item spectra in L2
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    __builtin_nontemporal_store(f2v{acc[2 * ss], acc[2 * ss + 1]}, reinterpret_cast<f2v *>(zo + ss * n2 + lane));
   });
   if constexpr (DW) {
     // fixed-order tree reduction of the lanes' dot products (NL = N^2 need

@@ -193,7 +193,9 @@ __global__ __launch_bounds__(FusedGeom<N>::NL, FusedGeom<N>::WPE) void k_gain_fu
       constexpr int u = decltype(uu)::value;
       static_for<0, H1>([&](auto k) {
         constexpr int kk = decltype(k)::value;
-        wout[kk * n2 + lane + u * NL] = cplx<float>{acc[u][2 * kk], acc[u][2 * kk + 1]};
+        typedef float f2v __attribute__((ext_vector_type(2)));   // streaming store, as below
+        __builtin_nontemporal_store(f2v{acc[u][2 * kk], acc[u][2 * kk + 1]},
+                                    reinterpret_cast<f2v *>(wout + kk * n2 + lane + u * NL));
       });
     });
     return;
@@ -229,7 +231,10 @@ __global__ __launch_bounds__(FusedGeom<N>::NL, FusedGeom<N>::WPE) void k_gain_fu
         constexpr int kk = decltype(k)::value;
         const long o = kk * n2 + lane + u * NL;
         const float a = ae[o];
-        wout[o] = cplx<float>{zr[u][kk] * a, zi[u][kk] * a};
+        // streaming store: the half spectra are read once, by the node sum,
+        // and should not evict the item spectra the other pairs reuse from L2
+        typedef float f2v __attribute__((ext_vector_type(2)));
+        __builtin_nontemporal_store(f2v{zr[u][kk] * a, zi[u][kk] * a}, reinterpret_cast<f2v *>(wout + o));
       });
     });
   }
