@@ -243,11 +243,13 @@ __global__ __launch_bounds__(256) void k_sum_nodes(const float4 *__restrict__ W,
   const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= nitems * n_in) return;
   const long b = i / n_in, o = i % n_in;
-  const float4 *w = W + b * Nr * n_in + o;
+  // each half spectrum is read once: streaming loads
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  const f4v *w = reinterpret_cast<const f4v *>(W + b * Nr * n_in + o);
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll 8
   for (int p = 0; p < Nr; ++p) {
-    const float4 v = w[p * n_in];
+    const f4v v = __builtin_nontemporal_load(w + p * n_in);
     acc.x += v.x;
     acc.y += v.y;
     acc.z += v.z;
