@@ -131,6 +131,19 @@ qcoll_status qcoll_plan_info(qcoll_plan plan, qcoll_plan_info_t *host_out);
 /* Copy the radial rule (HOST arrays of N_rho doubles each). */
 qcoll_status qcoll_plan_radial(qcoll_plan plan, double *host_rho, double *host_w);
 
+/* Copy one of the plan's kernel-mode tables from the device into a HOST
+ * array of exactly n doubles, in FP64 and without the 1/N^3 normalisation
+ * the kernels fold in (Appendix, quadrature form of G):
+ *   which 0: gain weights alpha_p(k) = 2 w_p F(k, rho_p), [N_rho][N^3] in DFT
+ *            index order (after SVD truncation, the truncated table
+ *            sum_s U_sp V_s(k)); ENOTSUP for VSS plans;
+ *   which 1: loss weights Lambda(k) = 2 sum_{p,q} w_p w_q F(2k, rho_p), [N^3];
+ *   which 2: per-node loss weights Lambda_p(k) (their sum over p is Lambda),
+ *            [N_rho][N^3]; untruncated VHS plans only (else ENOTSUP).
+ * Tables of FP32 plans are stored in FP32 and come back widened.  EINVAL if
+ * n does not match the table.  Synchronous. */
+qcoll_status qcoll_plan_table(qcoll_plan plan, int32_t which, double *host_out, size_t n);
+
 /* Change omega (and the prefactor if it follows omega) of an untruncated
  * plan; rebuilds the kernel tables synchronously.  ENOTSUP for truncated plans. */
 qcoll_status qcoll_plan_set_omega(qcoll_plan plan, double omega);

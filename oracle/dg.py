@@ -66,7 +66,11 @@ def eigen_factors(H, tol=1e-13):
     K = H.shape[0]
     rows, cols, ranks = [], [], []
     for m in range(K):
-        lam, U = np.linalg.eigh(0.5 * (H[m] + H[m].T))
+        # the eigen form needs H_m symmetric in (l1, l2); a tensor that is not
+        # (a mis-ordered index, say) is an error, not something to average away
+        if not np.allclose(H[m], H[m].T, rtol=0.0, atol=1e-14 * np.abs(H[m]).max()):
+            raise ValueError(f"triple tensor slice {m} is not symmetric in (l1, l2)")
+        lam, U = np.linalg.eigh(H[m])
         keep = np.abs(lam) > tol * np.abs(lam).max()
         ranks.append(int(keep.sum()))
         for r in np.nonzero(keep)[0]:

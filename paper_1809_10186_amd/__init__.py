@@ -72,6 +72,7 @@ def lib():
             "qcoll_plan_info": ([vp, ctypes.POINTER(PlanInfo)], i32),
             "qcoll_plan_radial": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], i32),
             "qcoll_plan_set_omega": ([vp, ctypes.c_double], i32),
+            "qcoll_plan_table": ([vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t], i32),
             "qcoll_plan_set_schedule": ([vp, i32], i32),
             "qcoll_workspace_bytes": ([vp, i64, i32], ctypes.c_size_t),
             "qcoll_eval": ([vp, i64, dp, dp, vp, ctypes.c_size_t, vp], i32),
@@ -170,6 +171,13 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _keep_for(t, stream):
+    """A temporary allocated on the current stream but used by kernels enqueued
+    on `stream`: tell the caching allocator not to reuse it before they finish."""
+    if stream is not None and t is not None:
+        t.record_stream(stream)
+
+
 class Plan:
     """A plan for one velocity grid and kernel.  See include/qcoll.h."""
 
@@ -188,7 +196,7 @@ class Plan:
         self._h = h
         self.N, self.L, self.N_rho = int(N), float(L), int(N_rho)
         self.precision = precision
-        self._ws = None
+        self._ws = {}
 
     def close(self):
         if getattr(self, "_h", None):
@@ -218,20 +226,49 @@ class Plan:
     def set_omega(self, omega):
         _check(lib().qcoll_plan_set_omega(self._h, float(omega)))
 
+    def table(self, which):
+        """Kernel-mode table as a float64 numpy array: "gain" [N_rho, N, N, N],
+        "loss" [N, N, N] or "loss_nodes" [N_rho, N, N, N] (see include/qcoll.h)."""
+        import numpy as np
+        code = {"gain": 0, "loss": 1, "loss_nodes": 2}[which]
+        n = self.N
+        shape = (n, n, n) if code == 1 else (self.N_rho, n, n, n)
+        out = np.empty(shape, dtype=np.float64)
+        _check(lib().qcoll_plan_table(self._h, code, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      out.size))
+        return out
+
     def set_schedule(self, schedule):
         """0 auto, 1 two-pass, 2 fused (see include/qcoll.h)."""
         _check(lib().qcoll_plan_set_schedule(self._h, int(schedule)))
-        self._ws = None
+        self._ws = {}
 
     def workspace_bytes(self, batch, op=0):
         return int(lib().qcoll_workspace_bytes(self._h, int(batch), int(op)))
 
-    def workspace(self, batch, op=0):
+    def workspace(self, batch, op=0, stream=None):
+        """The plan's cached workspace for `stream` (one buffer per stream, so that
+        calls on different streams never share scratch memory)."""
         import torch
         need = self.workspace_bytes(batch, op)
-        if self._ws is None or self._ws.numel() < need:
-            self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
-        return self._ws
+        s = torch.cuda.current_stream(self.device) if stream is None else stream
+        key = s.cuda_stream
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < need:
+            with torch.cuda.stream(s):
+                ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        return ws
+
+    def _check_out(self, t, name, shape, batch=None):
+        """An output buffer the library writes: float64, contiguous, on the plan's
+        device, of exactly `shape` (the kernels trust these sizes)."""
+        import torch
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.device != self.device:
+            raise ValueError(f"{name} must be a contiguous float64 tensor on {self.device}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+        return t
 
     def _check_f(self, t, name):
         import torch
@@ -247,7 +284,9 @@ class Plan:
         batch = self._check_f(f, "f")
         if out is None:
             out = torch.empty_like(f)
-        ws = self.workspace(batch, 0)
+        else:
+            self._check_out(out, "out", f.shape)
+        ws = self.workspace(batch, 0, stream)
         _check(lib().qcoll_eval(self._h, batch, _ptr(f), _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
         return out
 
@@ -259,14 +298,19 @@ class Plan:
             raise ValueError("f and g batches differ")
         if out is None:
             out = torch.empty_like(f)
+        else:
+            self._check_out(out, "out", f.shape)
         need = self.workspace_bytes(batch, 2)
         ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
         _check(lib().qcoll_eval_bilinear(self._h, batch, _ptr(f), _ptr(g), _ptr(out), _ptr(ws), ws.numel(),
                                          _stream(stream)))
+        _keep_for(ws, stream)
         return out
 
     def conserve(self, Q, moments=None, stream=None):
         batch = self._check_f(Q, "Q")
+        if moments is not None:
+            self._check_out(moments, "moments", (batch, 5))
         _check(lib().qcoll_conserve(self._h, batch, _ptr(Q), _ptr(moments), _stream(stream)))
         return Q
 
@@ -275,6 +319,8 @@ class Plan:
         batch = self._check_f(f, "f")
         if out is None:
             out = torch.empty(f.shape[:-3] + (14,), dtype=torch.float64, device=self.device)
+        else:
+            self._check_out(out, "out", f.shape[:-3] + (14,))
         _check(lib().qcoll_moments(self._h, batch, _ptr(f), _ptr(out), _stream(stream)))
         return out
 
@@ -282,12 +328,19 @@ class Plan:
             stream=None):
         import torch
         batch = self._check_f(f, "f")
-        self._check_f(g, "g")
-        if want_df and df is None:
-            df = torch.empty_like(f)
-        if want_domega and domega is None:
-            domega = torch.empty(batch, dtype=torch.float64, device=self.device)
-        ws = self.workspace(batch, 1)
+        if self._check_f(g, "g") != batch:
+            raise ValueError("f and g batches differ")
+        if want_df:
+            if df is None:
+                df = torch.empty_like(f)
+            else:
+                self._check_out(df, "df", f.shape)
+        if want_domega:
+            if domega is None:
+                domega = torch.empty(batch, dtype=torch.float64, device=self.device)
+            else:
+                self._check_out(domega, "domega", (batch,))
+        ws = self.workspace(batch, 1, stream)
         _check(lib().qcoll_vjp(self._h, batch, _ptr(f), _ptr(g), _ptr(df if want_df else None),
                                _ptr(domega if want_domega else None), int(bool(through_conserve)),
                                _ptr(ws), ws.numel(), _stream(stream)))
@@ -305,14 +358,20 @@ class Plan:
         R = T.shape[0]
         if T.shape != (R, K) or W.shape != (K, R):
             raise ValueError("T must be [R, K] and W [K, R]")
+        if F.device != self.device:
+            raise ValueError(f"F must be on {self.device}")
         T = T.to(device=self.device, dtype=torch.float64).contiguous()
         W = W.to(device=self.device, dtype=torch.float64).contiguous()
         if out is None:
             out = torch.empty_like(F)
+        else:
+            self._check_out(out, "out", F.shape)
         need = int(lib().qcoll_dg_workspace_bytes(self._h, E, K, R))
         ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
         _check(lib().qcoll_dg_collide(self._h, E, K, R, _ptr(T), _ptr(W), _ptr(F), _ptr(out), int(bool(conserve)),
                                       _ptr(ws), ws.numel(), _stream(stream)))
+        for t in (ws, T, W):
+            _keep_for(t, stream)
         return out
 
     def dg_collide_svd(self, F, T1, T2, W, conserve=False, out=None, stream=None):
@@ -325,18 +384,24 @@ class Plan:
         R = T1.shape[0]
         if T1.shape != (R, K) or T2.shape != (R, K) or W.shape != (K, R):
             raise ValueError("T1, T2 must be [R, K] and W [K, R]")
+        if F.device != self.device:
+            raise ValueError(f"F must be on {self.device}")
         T1, T2, W = [x.to(device=self.device, dtype=torch.float64).contiguous() for x in (T1, T2, W)]
         if out is None:
             out = torch.empty_like(F)
+        else:
+            self._check_out(out, "out", F.shape)
         need = int(lib().qcoll_dg_svd_workspace_bytes(self._h, E, K, R))
         ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
         _check(lib().qcoll_dg_collide_svd(self._h, E, K, R, _ptr(T1), _ptr(T2), _ptr(W), _ptr(F), _ptr(out),
                                           int(bool(conserve)), _ptr(ws), ws.numel(), _stream(stream)))
+        for t in (ws, T1, T2, W):
+            _keep_for(t, stream)
         return out
 
     def set_chunk(self, items):
         _check(lib().qcoll_plan_set_chunk(self._h, int(items)))
-        self._ws = None
+        self._ws = {}
 
     def autotune(self, f, Q=None, stream=None):
         """Time the candidate schedules on f and keep the fastest; returns (schedule, chunk)."""
@@ -344,12 +409,14 @@ class Plan:
         batch = self._check_f(f, "f")
         if Q is None:
             Q = torch.empty_like(f)
+        else:
+            self._check_out(Q, "Q", f.shape)
         need = int(lib().qcoll_autotune_workspace_bytes(self._h, batch))
         ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
         sch, ck = ctypes.c_int32(), ctypes.c_int32()
         _check(lib().qcoll_autotune(self._h, batch, _ptr(f), _ptr(Q), _ptr(ws), ws.numel(), _stream(stream),
                                     ctypes.byref(sch), ctypes.byref(ck)))
-        self._ws = None
+        self._ws = {}
         return sch.value, ck.value
 
     def poll(self):
@@ -519,9 +586,12 @@ def collide(f, plan, omega=None, conserve=True):
     """Differentiable Q(f,f) (optionally conservation-projected).
 
     f: float64 CUDA tensor [..., N, N, N].  omega: optional 0-d float64 tensor;
-    when given (requires_grad allowed) the plan's omega is set to its value and
-    its gradient is sum over the batch of g . dQ/d omega.  The backward pass
-    calls qcoll_vjp (through the projection when conserve is True).
+    when given (requires_grad allowed) the plan's omega is set to its value (and
+    stays set for later calls) and its gradient is sum over the batch of
+    g . dQ/d omega.  The backward pass calls qcoll_vjp (through the projection
+    when conserve is True) at the omega the forward pass used: it is saved with
+    the graph, so other calls that change the plan's omega in between do not
+    affect this backward.
     """
     import torch
 
@@ -534,6 +604,7 @@ def collide(f, plan, omega=None, conserve=True):
             if conserve:
                 plan.conserve(Q)
             ctx.save_for_backward(f_)
+            ctx.omega = plan.info()["omega"]
             return Q
 
         @staticmethod
@@ -541,8 +612,15 @@ def collide(f, plan, omega=None, conserve=True):
             (f_,) = ctx.saved_tensors
             want_f = ctx.needs_input_grad[0]
             want_w = len(ctx.needs_input_grad) > 1 and ctx.needs_input_grad[1]
-            df, dw = plan.vjp(f_.contiguous(), gQ.contiguous(), through_conserve=conserve,
-                              want_df=want_f, want_domega=want_w)
+            now = plan.info()["omega"]
+            if now != ctx.omega:
+                plan.set_omega(ctx.omega)
+            try:
+                df, dw = plan.vjp(f_.contiguous(), gQ.contiguous(), through_conserve=conserve,
+                                  want_df=want_f, want_domega=want_w)
+            finally:
+                if now != ctx.omega:
+                    plan.set_omega(now)
             return (df if want_f else None), (dw.sum().reshape(()) if want_w else None)
 
     return _Collide.apply(f, omega)

@@ -10,6 +10,7 @@
 namespace qcoll {
 qcoll_status plan_build(Plan &p, const qcoll_params &prm);
 qcoll_status plan_set_omega(Plan &p, double omega);
+qcoll_status plan_table(const Plan &p, int which, double *host, size_t n);
 void plan_free(Plan &p);
 
 static thread_local std::string g_err;
@@ -136,6 +137,13 @@ qcoll_status qcoll_plan_radial(qcoll_plan plan, double *rho, double *w) {
   return QCOLL_OK;
 }
 
+qcoll_status qcoll_plan_table(qcoll_plan plan, int32_t which, double *host_out, size_t n) {
+  if (!plan || !host_out) return fail(QCOLL_EINVAL, "NULL argument");
+  qcoll_status st = check_device(plan->p);
+  if (st != QCOLL_OK) return st;
+  return qcoll::plan_table(plan->p, which, host_out, n);
+}
+
 qcoll_status qcoll_plan_set_omega(qcoll_plan plan, double omega) {
   if (!plan) return fail(QCOLL_EINVAL, "plan is NULL");
   if (!(omega >= 0.5 && omega <= 1.0)) return fail(QCOLL_EINVAL, "omega must lie in [0.5, 1]");
@@ -151,6 +159,7 @@ qcoll_status qcoll_plan_set_schedule(qcoll_plan plan, int32_t schedule) {
     return fail(QCOLL_ENOTSUP, "the on-chip gain kernels need FP32 with N <= 32 or FP64 with N = 16");
   plan->p.schedule = schedule;
   plan->p.schedule_user = schedule;
+  ++plan->p.gen;
   return QCOLL_OK;
 }
 

@@ -49,6 +49,7 @@ struct qcoll_group_s {
   int device = 0;
   struct Cached {
     std::vector<const void *> ptrs;
+    std::vector<uint64_t> gens;   // plan generations at capture
     int32_t op = 0, flag = 0;
     void *ws = nullptr;
     hipStream_t st = nullptr;
@@ -112,15 +113,21 @@ qcoll_status run(qcoll_group g, int32_t op, const double *const *a, const double
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (!use_graph) return enqueue(g, op, a, b, out, out2, flag, ws, st);
 
+  // a captured graph bakes in the plans' table pointers, schedules and
+  // workspace layouts: the key holds every plan's generation besides the I/O
+  // pointers, so a change to any plan (omega, schedule, chunk, autotune)
+  // leads to a fresh capture
   std::vector<const void *> key;
+  std::vector<uint64_t> gens;
   for (size_t i = 0; i < g->plans.size(); ++i) {
     key.push_back(a[i]);
     key.push_back(b ? b[i] : nullptr);
     key.push_back(out[i]);
     key.push_back(out2 ? out2[i] : nullptr);
+    gens.push_back(g->plans[i]->p.gen);
   }
   for (auto &c : g->cache)
-    if (c.ptrs == key && c.op == op && c.flag == flag && c.ws == ws && c.st == st) {
+    if (c.ptrs == key && c.gens == gens && c.op == op && c.flag == flag && c.ws == ws && c.st == st) {
       if (hipGraphLaunch(c.exec, st) != hipSuccess) return gfail(QCOLL_EDEVICE, "hipGraphLaunch failed");
       return QCOLL_OK;
     }
@@ -152,6 +159,7 @@ qcoll_status run(qcoll_group g, int32_t op, const double *const *a, const double
   }
   qcoll_group_s::Cached c;
   c.ptrs = key;
+  c.gens = gens;
   c.op = op;
   c.flag = flag;
   c.ws = ws;
@@ -247,6 +255,7 @@ qcoll_status qcoll_plan_set_chunk(qcoll_plan plan, int32_t items) {
   if (!plan) return gfail(QCOLL_EINVAL, "plan is NULL");
   if (items < 0 || items > 65536) return gfail(QCOLL_EINVAL, "chunk must be 0..65536");
   plan->p.chunk = items;
+  ++plan->p.gen;
   return QCOLL_OK;
 }
 
@@ -305,6 +314,7 @@ qcoll_status qcoll_autotune(qcoll_plan plan, int64_t batch, const double *f, dou
           (sch != 2 || qcoll::onchip_schedule_supported(p.N, p.precision))) {
         p.schedule = sch;
         p.chunk = ck;
+        ++p.gen;
         if (host_schedule) *host_schedule = sch;
         if (host_chunk) *host_chunk = ck;
         return QCOLL_OK;
@@ -350,6 +360,7 @@ qcoll_status qcoll_autotune(qcoll_plan plan, int64_t batch, const double *f, dou
   qcoll_timing_enable(timing);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  ++p.gen;   // the trial schedules changed the plan's layout
   if (rc != QCOLL_OK) return rc;
   p.schedule = bs;
   p.chunk = bc;

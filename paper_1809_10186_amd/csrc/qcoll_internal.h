@@ -24,6 +24,7 @@ struct Plan {
   int schedule = 0;              // hot-loop schedule: 0 auto, 1 two-pass, 2 fused
   int schedule_user = 0;         // the schedule last requested through the API (the autotuner leaves it)
   int chunk = 0;                 // items per eval chunk (0: default 64)
+  uint64_t gen = 0;              // bumped whenever tables, schedule or chunk change (keys cached graphs)
   double sigma_max = 0, sigma_min_kept = 0;
 
   std::vector<double> rho, w_rho;          // radial rule

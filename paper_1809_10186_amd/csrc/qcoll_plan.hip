@@ -582,10 +582,91 @@ qcoll_status plan_set_omega(Plan &p, double omega) {
     set_error("hipDeviceSynchronize failed");
     return QCOLL_EDEVICE;
   }
+  // build the new tables beside the old ones and swap them in only on
+  // success: a failed rebuild leaves the plan as it was
+  Plan t = p;
+  t.alpha_eff = t.alpha_pq = nullptr;
+  t.V = t.lam = t.umix_d = nullptr;
+  t.lam_p = t.dlog = nullptr;
+  t.omega = omega;
+  if (t.b_follows_omega) t.b = kernel_constant(t.omega, t.vss);
+  const qcoll_status st = t.is_vss() ? upload_vss_tables(t) : upload_kernel_tables(t);
+  if (st != QCOLL_OK) {
+    free_kernel_tables(t);
+    return st;
+  }
   free_kernel_tables(p);
-  p.omega = omega;
-  if (p.b_follows_omega) p.b = kernel_constant(p.omega, p.vss);
-  return p.is_vss() ? upload_vss_tables(p) : upload_kernel_tables(p);
+  p = t;
+  ++p.gen;
+  return QCOLL_OK;
+}
+
+// Copy a device table back to the host in FP64, undoing the 1/N^3 the kernels fold in.
+template <typename T>
+static qcoll_status fetch(const void *d, size_t n, std::vector<double> &out) {
+  std::vector<T> t(n);
+  if (hipMemcpy(t.data(), d, n * sizeof(T), hipMemcpyDeviceToHost) != hipSuccess) {
+    set_error("hipMemcpy failed while reading a plan table");
+    return QCOLL_EDEVICE;
+  }
+  out.assign(t.begin(), t.end());
+  return QCOLL_OK;
+}
+
+qcoll_status plan_table(const Plan &p, int which, double *host, size_t n) {
+  const long n3 = p.n3();
+  const double scale = double(n3);
+  std::vector<double> t;
+  qcoll_status st;
+  if (which == 0) {
+    if (p.is_vss()) {
+      set_error("VSS plans have per-(p, q) gain weights, not a per-node table");
+      return QCOLL_ENOTSUP;
+    }
+    if (n != size_t(p.N_rho) * n3) {
+      set_error("the gain-weight table has N_rho * N^3 entries");
+      return QCOLL_EINVAL;
+    }
+    const size_t rows = size_t(2 * p.npair());
+    st = p.precision == QCOLL_FP32 ? fetch<float>(p.V, rows * n3, t) : fetch<double>(p.V, rows * n3, t);
+    if (st != QCOLL_OK) return st;
+    // alpha~_p = sum_s U[s][p] V_s (U = I when the plan does not mix)
+    for (int q = 0; q < p.N_rho; ++q)
+      for (long k = 0; k < n3; ++k) {
+        double acc = 0.0;
+        if (p.mix_identity) {
+          acc = t[size_t(q) * n3 + k];
+        } else {
+          for (int r = 0; r < p.nv; ++r) acc += p.umix[size_t(r) * p.N_rho + q] * t[size_t(r) * n3 + k];
+        }
+        host[size_t(q) * n3 + k] = acc * scale;
+      }
+    return QCOLL_OK;
+  }
+  if (which == 1) {
+    if (n != size_t(n3)) {
+      set_error("the loss-weight table has N^3 entries");
+      return QCOLL_EINVAL;
+    }
+    if ((st = fetch<double>(p.lam, n, t)) != QCOLL_OK) return st;
+    for (size_t k = 0; k < n; ++k) host[k] = t[k] * scale;
+    return QCOLL_OK;
+  }
+  if (which == 2) {
+    if (!p.lam_p) {
+      set_error("per-node loss weights exist for untruncated VHS plans only");
+      return QCOLL_ENOTSUP;
+    }
+    if (n != size_t(p.N_rho) * n3) {
+      set_error("the per-node loss-weight table has N_rho * N^3 entries");
+      return QCOLL_EINVAL;
+    }
+    if ((st = fetch<double>(p.lam_p, n, t)) != QCOLL_OK) return st;
+    std::copy(t.begin(), t.end(), host);
+    return QCOLL_OK;
+  }
+  set_error("unknown table");
+  return QCOLL_EINVAL;
 }
 
 void plan_free(Plan &p) {

@@ -2,6 +2,7 @@
 import numpy as np
 import pytest
 
+import oracle_pool
 import workloads as W
 from oracle import adjoint
 from oracle import conserve as oc
@@ -247,3 +248,67 @@ def test_two_pass_vjp_independent_of_chunking(precision, N, L):
         assert torch.equal(d1, df[lo:hi])
         assert torch.equal(w1, dw[lo:hi])
     plan.close()
+
+
+@pytest.mark.timeout(900)
+def test_uneven_48_vjp_against_oracle_and_fp64():
+    """The 48^3 grid of the uneven batch (307 points, L = 9, N_rho = 24, M = 12,
+    SVD 1e-6), FP32 two-pass VJP through the projection in the group's launch
+    configuration: three items against the oracle's FP64 adjoint, every item
+    against the FP64 plan (the same truncated gain table)."""
+    com = W.UNEVEN_COMMON
+    g48 = W.UNEVEN[2]
+    N, L, Nr, M = g48["N"], g48["L"], g48["N_rho"], com["M"]
+    sph = W.sphere_rule(M)
+    f = W.uneven_grid(2)
+    g = W.cotangent(f, 9002)
+    fg, gg = gpu(f), gpu(g)
+    print(f"case vjp 48^3: {f.shape[0]} items", flush=True)
+    p32 = qc.Plan(N, L, Nr, sphere=sph, omega=com["omega"], svd_rank=0, svd_tol=com["svd_tol"],
+                  precision=qc.QCOLL_FP32)
+    p64 = qc.Plan(N, L, Nr, sphere=sph, omega=com["omega"], svd_rank=0, svd_tol=com["svd_tol"],
+                  precision=qc.QCOLL_FP64)
+    assert p32.info()["rank"] == p64.info()["rank"]
+    df32, _ = p32.vjp(fg, gg, through_conserve=True)
+    df64, _ = p64.vjp(fg, gg, through_conserve=True)
+    e_all = float(((df32 - df64).abs().amax(dim=(1, 2, 3)) / df64.abs().amax(dim=(1, 2, 3))).max())
+    print(f"48^3 FP32 vs FP64 plan, every item: max rel {e_all:.3e}", flush=True)
+    idx = [0, 150, 306]
+    ref = oracle_pool.vjp_many(f[idx], g[idx], project=True, N=N, L=L, N_rho=Nr, M=M, omega=com["omega"],
+                               svd_tol=com["svd_tol"])
+    e64 = rel(df64.cpu().numpy()[idx], ref)
+    e32 = rel(df32.cpu().numpy()[idx], ref)
+    print(f"48^3 vs oracle: FP64 {e64:.3e} FP32 {e32:.3e}", flush=True)
+    assert e64 <= TOL[qc.QCOLL_FP64]
+    assert e32 <= TOL[qc.QCOLL_FP32]
+    assert e_all <= TOL[qc.QCOLL_FP32]
+
+
+def test_autograd_two_omegas_before_one_backward():
+    """Two collide calls at different omegas on one plan, then one backward
+    through both: each part's gradient is taken at its own forward's omega
+    (equal to separate backwards), and the plan keeps the last omega set."""
+    N, L, Nr = 12, 5.0, 6
+    sph = W.sphere_rule(12)
+    plan = qc.Plan(N, L, Nr, sphere=sph, omega=0.81, precision=qc.QCOLL_FP64)
+    f0 = W.maxwellian_mixture(2, N, L, 95)
+    g1 = gpu(W.cotangent(f0, 96))
+    g2 = gpu(W.cotangent(f0, 97))
+    f = gpu(f0).requires_grad_(True)
+    o1 = torch.tensor(0.7, dtype=torch.float64, device="cuda", requires_grad=True)
+    o2 = torch.tensor(0.9, dtype=torch.float64, device="cuda", requires_grad=True)
+    Q1 = qc.collide(f, plan, omega=o1, conserve=True)
+    Q2 = qc.collide(f, plan, omega=o2, conserve=True)
+    ((Q1 * g1).sum() + (Q2 * g2).sum()).backward()
+    assert plan.info()["omega"] == 0.9
+    ref_df = torch.zeros_like(f)
+    ref_dw = []
+    for om, gq in ((0.7, g1), (0.9, g2)):
+        p = qc.Plan(N, L, Nr, sphere=sph, omega=om, precision=qc.QCOLL_FP64)
+        df, dw = p.vjp(f.detach(), gq, through_conserve=True, want_domega=True)
+        ref_df += df
+        ref_dw.append(float(dw.sum()))
+        p.close()
+    assert torch.allclose(f.grad, ref_df, rtol=0, atol=1e-13 * float(ref_df.abs().max()))
+    assert abs(float(o1.grad) - ref_dw[0]) <= 1e-12 * abs(ref_dw[0])
+    assert abs(float(o2.grad) - ref_dw[1]) <= 1e-12 * abs(ref_dw[1])

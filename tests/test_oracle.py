@@ -250,6 +250,36 @@ def test_moments_of_maxwellian():
     assert np.allclose(mo[11:], 0, atol=1e-10)
 
 
+def test_moments_of_two_maxwellian_mixture_closed_form():
+    """Moments of a sum of two drifting Maxwellians n_i (pi T_i)^{-3/2}
+    exp(-|c - u_i|^2 / T_i), whose values follow in closed form from the
+    Gaussian moments (per unit density, v = c - u_i has covariance T_i/2 I):
+      n = n1 + n2, u = (n1 u1 + n2 u2) / n, d_i = u_i - u,
+      T = 2/(3n) sum_i n_i (3 T_i / 2 + |d_i|^2),
+      P = sum_i n_i (T_i I + 2 d_i d_i^T)          (P = 2 int f (c-u)(c-u)^T),
+      q = sum_i n_i d_i (5 T_i / 2 + |d_i|^2)       (q = int f (c-u)|c-u|^2).
+    The drifts are not along the axes, so P has off-diagonal parts and q is
+    non-zero: a wrong factor in either (a dropped 2, a halved q) fails.  The
+    midpoint rule on this grid is accurate to far below the tolerance (spacing
+    1/4 against widths T_i >= 1; tails beyond |c| = 8 below 1e-14)."""
+    N, L = 64, 8.0
+    n = np.array([0.7, 1.2])
+    T = np.array([1.0, 1.5])
+    us = np.array([[0.6, -0.4, 0.3], [-0.2, 0.5, -0.45]])
+    f = sum(W.maxwellian(N, L, n[i], us[i], T[i]) for i in range(2))
+    mo = conserve.moments(f, N, L)
+    nt = n.sum()
+    u = (n[:, None] * us).sum(axis=0) / nt
+    d = us - u
+    d2 = (d ** 2).sum(axis=1)
+    Tt = 2.0 / (3.0 * nt) * np.sum(n * (1.5 * T + d2))
+    Pt = sum(n[i] * (T[i] * np.eye(3) + 2.0 * np.outer(d[i], d[i])) for i in range(2))
+    qt = sum(n[i] * d[i] * (2.5 * T[i] + d2[i]) for i in range(2))
+    exp = np.array([nt, *u, Tt, Pt[0, 0], Pt[0, 1], Pt[0, 2], Pt[1, 1], Pt[1, 2], Pt[2, 2], *qt])
+    assert abs(Pt[0, 1]) > 0.05 and np.abs(qt).min() > 0.05   # the pin is not degenerate
+    assert np.abs(mo - exp).max() < 1e-12
+
+
 # ---------------------------------------------------------------- adjoint
 def test_vjp_f_matches_central_difference():
     N, L = 8, 5.0
@@ -308,6 +338,38 @@ def test_dg_triple_tensor_properties():
     H2 = dg.triple_tensor_2d(1)
     assert H2.shape == (4, 4, 4)
     assert abs(H2.sum() - 4.0) < 1e-13   # integral of 1 over [-1,1]^2
+
+
+@pytest.mark.parametrize("P", [1, 2])
+def test_dg_triple_tensor_2d_against_direct_quadrature(P):
+    """The 2-D tensor of the quadrilateral basis phi_(i,j)(x, y) = phi_i(x) phi_j(y),
+    ordered as (i, j) -> i (P+1) + j, pinned three ways: every entry against a
+    direct 2-D Gauss product rule of the three 2-D basis functions evaluated as
+    functions of (x, y); symmetry in (l1, l2) and in (m, l1); and sum_m H =
+    the mass matrix, diag(w_i w_j) on the Gauss-node basis (partition of unity).
+    A permuted Kronecker index order passes the total-sum check but none of these."""
+    from oracle import dg
+    H = dg.triple_tensor_2d(P)
+    K1 = P + 1
+    nodes, w = dg.gauss_nodes(P)
+    xq, wq = np.polynomial.legendre.leggauss(2 * P + 3)
+    X, Y = np.meshgrid(xq, xq, indexing="ij")
+    WW = np.outer(wq, wq)
+
+    def phi2(i, j):
+        return dg.lagrange(nodes, X.ravel())[i].reshape(X.shape) * dg.lagrange(nodes, Y.ravel())[j].reshape(Y.shape)
+
+    basis = [phi2(i, j) for i in range(K1) for j in range(K1)]
+    ref = np.array([[[np.sum(WW * bm * ba * bb) for bb in basis] for ba in basis] for bm in basis])
+    assert np.abs(H - ref).max() < 1e-14
+    assert np.allclose(H, H.transpose(0, 2, 1), rtol=0, atol=1e-15)
+    assert np.allclose(H, H.transpose(1, 0, 2), rtol=0, atol=1e-15)
+    assert np.allclose(H.sum(axis=0), np.diag(np.outer(w, w).ravel()), rtol=0, atol=1e-14)
+    # the eigen factorisation refuses a tensor that is not symmetric in (l1, l2)
+    bad = H.copy()
+    bad[0, 0, 1] += 1e-3
+    with pytest.raises(ValueError):
+        dg.eigen_factors(bad)
 
 
 def test_dg_eigen_form_equals_direct_double_sum():
