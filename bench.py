@@ -69,12 +69,71 @@ def cpu_baseline(f, prm, n_items):
                       f"{dt:.1f} s wall on {min(cores, n)} processes"}, dict(res)
 
 
+def model_flops_fft(N):
+    """Model flops of one complex 3-D transform of n = N^3 points: 5 n log2 n."""
+    n3 = N ** 3
+    return 5.0 * n3 * math.log2(n3)
+
+
 def model_flops_per_term(N):
     """Model flops of one (item, rho_p, sigma_q) term of the hot loop: one complex
-    3-D transform (5 n log2 n with n = N^3) plus the multiplier, the product and
-    the accumulation (10 flops per point)."""
-    n3 = N ** 3
-    return 5.0 * n3 * math.log2(n3) + 10.0 * n3
+    3-D transform plus 23 pointwise flops per point (the shift multiplier, the
+    product of the two shifted copies and the weighted accumulation)."""
+    return model_flops_fft(N) + 23.0 * N ** 3
+
+
+def algorithmic_bytes(role, fp32, B, N, Nr, M, npair, nv):
+    """Bytes per step that a pass of the pipeline must move through HBM (item
+    data only; the shared plan tables are read from cache): what each kernel
+    role reads and writes once, by the layout of the workspace.  None for roles
+    without a byte model."""
+    es = 4 if fp32 else 8           # working precision of the gain
+    c = 2 * es                      # complex in the working precision
+    n3, nh = N ** 3, (N // 2 + 1) * N * N
+    half = fp32                     # the fused schedule keeps half spectra
+    m = {
+        "forward slab": B * n3 * (8 + 16),
+        "forward pencil": B * n3 * ((16 + 16 + 8) if fp32 else (16 + 16)),
+        "gain slab": B * Nr * M * n3 * (c + c),
+        "gain pencil": B * Nr * n3 * (M * c + es),
+        "mix": B * n3 * (Nr + nv) * es,
+        "low-rank slab": B * npair * n3 * (2 * es + c),
+        "low-rank pencil": B * n3 * (npair * c + c),
+        "gain inverse slab": B * (nh if half else n3) * (c + c),
+        "loss slab": B * (nh if half else n3) * (16 + 16),
+        "assemble": B * ((nh * (c + 16) + n3 * 16) if half else n3 * (c + 16 + 16)),
+        "sum nodes": B * nh * 8 * (Nr + 1),
+        "conserve": B * n3 * (8 + 8),
+        "gain fused": B * n3 * 8 + B * Nr * nh * 8,
+    }
+    return m.get(role)
+
+
+def hbm_passes(kt, steps, fp32, B, N, Nr, M, npair, nv):
+    """Per kernel role: time per step, algorithmic bytes per step and the rate
+    against the HBM peak (the on-chip gain kernel is ALU bound and listed
+    with its bytes only)."""
+    out = {}
+    tot_b = tot_ms = 0.0
+    for role, (ms, n) in sorted(kt.items(), key=lambda kv: -kv[1][0]):
+        b = algorithmic_bytes(role, fp32, B, N, Nr, M, npair, nv)
+        ms_step = ms / steps
+        ent = {"ms_per_step": round(ms_step, 4), "launches_per_step": n / steps}
+        if b is not None:
+            gbs = b / (ms_step * 1e-3) / 1e9
+            ent.update({"algorithmic_MB": round(b / 1e6, 2), "GB_per_s": round(gbs, 1),
+                        "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
+            if role != "gain fused":
+                tot_b += b
+                tot_ms += ms_step
+        out[role] = ent
+    summary = None
+    if tot_ms > 0:
+        gbs = tot_b / (tot_ms * 1e-3) / 1e9
+        summary = {"roles": "every slab/pencil/reduction pass through HBM", "ms_per_step": round(tot_ms, 4),
+                   "algorithmic_MB": round(tot_b / 1e6, 1), "GB_per_s": round(gbs, 1),
+                   "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    return out, summary
 
 
 def measured_traffic(kernel, items_per_launch):
@@ -106,16 +165,18 @@ def source_digest(files):
     return h.hexdigest()
 
 
-def roofline(name, tot_ms, launches, steps, B, N, Nr, M):
+def roofline(name, tot_ms, launches, steps, B, N, Nr, M, fp32=True, npair=0, nv=0):
     """Roofline entry of the dominant kernel.  Units per launch are explained in
     DESIGN.md (section "Kernels and their rooflines")."""
-    n3 = N ** 3
     avg_ms = tot_ms / launches
+    key = name if fp32 else f"{name} fp64"
     base = {"kernel": name, "avg_launch_ms": round(avg_ms, 4), "launches": launches,
-            "traffic": measured_traffic(name, B * steps / launches)}
+            "traffic": measured_traffic(key, B * steps / launches)}
     if name == "gain fused":
         # ALU bound: model flops of every (item, p, q) term of the timed region
-        flops = B * Nr * M * steps * model_flops_per_term(N)
+        # plus the forward transform of every (item, p) accumulator (the
+        # low-rank stage the kernel runs on chip)
+        flops = B * Nr * steps * (M * model_flops_per_term(N) + model_flops_fft(N))
         per_launch = flops / launches
         achieved = per_launch / (avg_ms * 1e-3) / 1e12
         base.update({"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_VALU_PEAK,
@@ -123,13 +184,8 @@ def roofline(name, tot_ms, launches, steps, B, N, Nr, M):
                      "flops_per_launch": per_launch,
                      "peak_nonpacked_fp32": FP32_VALU_NONPACKED})
         return base
-    es = 4
-    if name == "gain slab":        # 8 B in + 8 B out per point per (item, p, q) task
-        total = 2 * 2 * es * n3 * B * Nr * M * steps
-    elif name == "gain pencil":    # 8 M B in + 4 B out per point per (item, p) pair
-        total = (2 * es * n3 * M + es * n3) * B * Nr * steps
-    else:
-        total = None
+    b = algorithmic_bytes(name, fp32, B, N, Nr, M, npair, nv)
+    total = None if b is None else b * steps
     if total is None:
         base.update({"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None})
         return base
@@ -195,6 +251,14 @@ def extras(qc, torch, W, reps=3):
             c[m] = lam[r]
             cols.append(c)
     forms["eigen"] = (np.array(rows), np.array(cols).T)
+    # collocation form through its own entry point: no contraction (T = I), the
+    # weights folded into the last store (W = diag(w)); same 192 evaluations as
+    # the headline step
+    Cout = torch.empty_like(F)
+    plan.autotune(F.reshape(-1, w["N"], w["N"], w["N"]))
+    ms = timeit(lambda: plan.dg_collide_collocated(F, wg, conserve=True, out=Cout))
+    out["dg_collide_collocated"] = {"elements": E, "K": K, "R": K, "ms": round(ms, 3),
+                                    "q_evals_per_s": round(E * K / (ms * 1e-3), 1)}
     for name, (T, Wm) in forms.items():
         Tg = torch.from_numpy(np.ascontiguousarray(T)).to("cuda")
         Wg = torch.from_numpy(np.ascontiguousarray(Wm)).to("cuda")
@@ -293,16 +357,72 @@ def extras(qc, torch, W, reps=3):
     grp = qc.Group(plans, [gdef["items"] for gdef in W.UNEVEN])
     Qs = [torch.empty_like(x) for x in fs]
     dfs = [torch.empty_like(x) for x in fs]
+    grp.autotune(fs, Qs)          # every member plan, before the graph is captured
     n = sum(gdef["items"] for gdef in W.UNEVEN)
     with torch.cuda.stream(stream):
         ms = timeit(lambda: grp.eval(fs, Qs=Qs, conserve=True, use_graph=True, stream=stream))
         ms_v = timeit(lambda: grp.vjp(fs, gs, dfs=dfs, through_conserve=True, use_graph=True, stream=stream))
+    # each branch alone (eager, the same tuned plan): the group's time against
+    # its longest branch shows whether the critical path or the launch
+    # structure bounds the group
+    branch = {}
+    for pl, fi, gi, qi, di, gdef in zip(plans, fs, gs, Qs, dfs, W.UNEVEN):
+        e_ms = timeit(lambda: (pl.eval(fi, qi), pl.conserve(qi)))
+        v_ms = timeit(lambda: pl.vjp(fi, gi, df=di, through_conserve=True))
+        branch[f"{gdef['N']}^3 x {gdef['items']}"] = {"eval_ms": round(e_ms, 3), "vjp_ms": round(v_ms, 3)}
     out["group_uneven"] = {"items": n, "grids": "1024 x 24^3 + 717 x 32^3 + 307 x 48^3",
                            "eval_ms": round(ms, 3), "evals_per_s": round(n / (ms * 1e-3), 1),
-                           "vjp_ms": round(ms_v, 3), "vjps_per_s": round(n / (ms_v * 1e-3), 1)}
+                           "vjp_ms": round(ms_v, 3), "vjps_per_s": round(n / (ms_v * 1e-3), 1),
+                           "branches_alone": branch,
+                           "sum_of_branches_eval_ms": round(sum(b["eval_ms"] for b in branch.values()), 3),
+                           "sum_of_branches_vjp_ms": round(sum(b["vjp_ms"] for b in branch.values()), 3)}
     grp.close()
     for pl in plans:
         pl.close()
+    return out
+
+
+def uneven48(qc, torch, W, steps, warmup):
+    """The 48^3 grid of the uneven batch alone (the group's critical path):
+    autotuned eval + conserve and the VJP through the projection, per-kernel
+    breakdown with algorithmic bytes (for profiler runs)."""
+    com, g = W.UNEVEN_COMMON, W.UNEVEN[2]
+    N, Nr, M = g["N"], g["N_rho"], com["M"]
+    sph = W.sphere_rule(M)
+    plan = qc.Plan(N, g["L"], Nr, sphere=sph, omega=com["omega"], svd_rank=0, svd_tol=com["svd_tol"],
+                   precision=qc.QCOLL_FP32)
+    f_np = W.uneven_grid(2)
+    f = torch.from_numpy(f_np).to("cuda")
+    gq = torch.from_numpy(W.cotangent(f_np, 10 + 2)).to("cuda")
+    B = f.shape[0]
+    Q, df = torch.empty_like(f), torch.empty_like(f)
+    tuned = plan.autotune(f, Q)
+    inf = plan.info()
+    out = {"workload": f"uneven batch, 48^3 grid: {B} points, L={g['L']}, N_rho={Nr}, M={M}, rank {inf['rank']}",
+           "autotuned_schedule_chunk": tuned}
+    for name, fn in (("eval_conserve", lambda: (plan.eval(f, Q), plan.conserve(Q))),
+                     ("vjp", lambda: plan.vjp(f, gq, df=df, through_conserve=True))):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        qc.timing_reset()
+        qc.timing_select(None)
+        qc.timing_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps * 1e3
+        qc.timing_enable(False)
+        kt = qc.timing_read()
+        ent = {"ms": round(dt, 3)}
+        if name == "eval_conserve":
+            passes, summ = hbm_passes(kt, steps, True, B, N, Nr, M, (inf["rank"] + 1) // 2, inf["rank"])
+            ent.update({"hbm_passes": passes, "hbm_passes_total": summ})
+        else:
+            ent["kernel_ms"] = {k: round(v[0] / steps, 4) for k, v in kt.items()}
+        out[name] = ent
+    plan.close()
     return out
 
 
@@ -317,6 +437,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary measurements (DG, VJP, groups)")
     ap.add_argument("--schedule", type=int, default=0, help="hot-loop schedule of the FP32 plan (0 auto)")
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--only", choices=("both", "fp32", "fp64", "uneven48"), default="both",
+                    help="time one path only and print its breakdown (for profiler runs); uneven48: the 48^3 "
+                         "grid of the uneven batch (307 points, FP32 + fix), eval + conserve and the VJP")
     a = ap.parse_args()
     if a.copy_probe:
         copy_probe()
@@ -329,6 +452,10 @@ def main():
     import torch
     import paper_1809_10186_amd as qc
     import workloads as W
+
+    if a.only == "uneven48":
+        print(json.dumps(uneven48(qc, torch, W, a.steps, a.warmup)))
+        return
 
     w = W.WORKLOADS[WORKLOAD]
     N, L, B = w["N"], w["L"], w["items"]
@@ -361,37 +488,57 @@ def main():
         return time.perf_counter() - t0
 
     p32, p64 = plans[qc.QCOLL_FP32], plans[qc.QCOLL_FP64]
-    for _ in range(a.warmup):
-        step(p32)
-    torch.cuda.synchronize()
-    # per-kernel breakdown: a short untimed pass with every kernel role timed
-    n_brk = min(a.steps, 5)
-    qc.timing_reset()
-    qc.timing_select(None)
-    qc.timing_enable(True)
-    run_steps(p32, n_brk)
-    qc.timing_enable(False)
-    kt_all = qc.timing_read()
-    dominant = max(kt_all.items(), key=lambda kv: kv[1][0])[0]
-    # timed region: hipEvents on the dominant kernel only (on its launch stream)
-    qc.timing_reset()
-    qc.timing_select(dominant)
-    qc.timing_enable(True)
-    dt32 = run_steps(p32, a.steps)
-    qc.timing_enable(False)
-    tot_ms, launches = qc.timing_read()[dominant]
-    qc.timing_select(None)
-    for _ in range(a.warmup):
-        step(p64)
-    torch.cuda.synchronize()
-    dt64 = run_steps(p64, a.steps)
-    ms32 = dt32 / a.steps * 1e3
-    ms64 = dt64 / a.steps * 1e3
+    Nr, M = w["N_rho"], w["M"]
+
+    def measure(plan, fp32):
+        """Warm-up, a short untimed pass with every kernel role timed (the
+        per-kernel breakdown), then the timed steps with hipEvents around the
+        dominant kernel only (on its launch stream)."""
+        for _ in range(a.warmup):
+            step(plan)
+        torch.cuda.synchronize()
+        n_brk = min(a.steps, 5)
+        qc.timing_reset()
+        qc.timing_select(None)
+        qc.timing_enable(True)
+        run_steps(plan, n_brk)
+        qc.timing_enable(False)
+        kt_all = qc.timing_read()
+        dominant = max(kt_all.items(), key=lambda kv: kv[1][0])[0]
+        many = kt_all[dominant][1] > 4 * n_brk
+        if many:
+            # a dominant kernel launched many times per step (the FP64 two-pass
+            # hot loop: 96 launches) would carry an event pair per launch in
+            # the timed region: time the steps clean, then the same number of
+            # steps again with the events for its launch duration
+            dt = run_steps(plan, a.steps)
+        qc.timing_reset()
+        qc.timing_select(dominant)
+        qc.timing_enable(True)
+        dt_ev = run_steps(plan, a.steps)
+        qc.timing_enable(False)
+        tot_ms, launches = qc.timing_read()[dominant]
+        qc.timing_select(None)
+        if not many:
+            dt = dt_ev
+        inf = plan.info()
+        npair, nv = (inf["rank"] + 1) // 2, inf["rank"]
+        roof = roofline(dominant, tot_ms, launches, a.steps, B, N, Nr, M, fp32=fp32, npair=npair, nv=nv)
+        passes, summ = hbm_passes(kt_all, n_brk, fp32, B, N, Nr, M, npair, nv)
+        return dt / a.steps * 1e3, roof, passes, summ
+
+    ms32 = ms64 = None
+    roof = roof64 = passes32 = passes64 = summ32 = summ64 = None
+    if a.only in ("both", "fp32"):
+        ms32, roof, passes32, summ32 = measure(p32, True)
+    if a.only in ("both", "fp64"):
+        ms64, roof64, passes64, summ64 = measure(p64, False)
+    if a.only != "both":
+        print(json.dumps({"only": a.only, "ms_per_step": ms32 or ms64, "roofline": roof or roof64,
+                          "hbm_passes": passes32 or passes64, "hbm_passes_total": summ32 or summ64}))
+        return
 
     info = p32.info()
-    roof = roofline(dominant, tot_ms, launches, a.steps, B, N, w["N_rho"], w["M"])
-    kernel_ms = {k: round(v[0] / n_brk, 4) for k, v in kt_all.items()}
-    Nr, M = w["N_rho"], w["M"]
 
     extra = None if a.no_extras else extras(qc, torch, W)
 
@@ -401,11 +548,12 @@ def main():
         # about 10-20 s of oracle work: 12 items per host core (one item ~1 s), at most the batch
         n_cpu = a.cpu_items or min(12 * min(os.cpu_count() or 1, 16), B)
         prm = dict(N=N, L=L, N_rho=Nr, M=M, omega=w["omega"], svd_tol=w["svd_tol"])
-        sample = [0, B // 2, B - 1]
         cpu, ref = cpu_baseline(f_np[:max(n_cpu, 1)], prm, n_cpu) if not a.no_cpu else (None, {})
         if not a.no_acc:
             from oracle import spectral
             from oracle import conserve as oc
+            # every item the CPU leg computed, else three sampled items
+            sample = sorted(ref) if ref else [0, B // 2, B - 1]
             P = spectral.Params(N, L, Nr, sph[0], sph[1], w["omega"], svd_tol=w["svd_tol"])
             refs = {}
             for i in sample:
@@ -417,9 +565,10 @@ def main():
             for prec, tag in ((qc.QCOLL_FP32, "fp32_fix"), (qc.QCOLL_FP64, "fp64")):
                 step(plans[prec])
                 Qh = Q.cpu().numpy()
-                err = max(np.abs(Qh[i] - refs[i]).max() / np.abs(refs[i]).max() for i in sample)
-                acc[tag] = err
-            acc["items"] = sample
+                errs = [np.abs(Qh[i] - refs[i]).max() / np.abs(refs[i]).max() for i in sample]
+                acc[tag] = float(max(errs))
+                acc[tag + "_conservation_residual"] = float(oc.conservation_residual(Qh, N, L).max())
+            acc["items"] = len(sample)
 
     out = {
         "metric": METRIC,
@@ -432,7 +581,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (f64 conservation fix)",
+        "dtype": "f32 (gain transforms and products; f64 spectrum, loss, assembly, conservation)",
         "data": "synthetic",
         "config": {"workload": "1D DG batch: 64 elements x 3 Gauss points = 192 points, N=32^3, L=6, "
                                "M=12, N_rho=16, VHS omega=0.81, SVD rank at 1e-8",
@@ -441,7 +590,8 @@ def main():
         "fp64": {"value": round(B / (ms64 * 1e-3), 1), "unit": "evals/s", "ms_per_step": round(ms64, 4)},
         "rel_linf_err": acc,
         "roofline": roof,
-        "kernel_ms_per_step": kernel_ms,
+        "hbm_passes": {"fp32": passes32, "fp32_total": summ32, "fp64": passes64, "fp64_total": summ64},
+        "roofline_fp64": roof64,
         "secondary": extra,
         "cpu_baseline": cpu,
     }

@@ -27,9 +27,10 @@
  *   anything is enqueued and then nothing is enqueued.
  * - Boundary data are FP64 in both precisions; QCOLL_FP32 computes the
  *   transforms and products in FP32 and returns FP64.
- * - Nyquist mode: the DFT index N/2 (frequency -N/2) is shifted as the cosine
- *   mode of the real trigonometric interpolant, factor cos(pi (N/2) s_d / L)
- *   per axis, so every intermediate of Q(f,f) is real.
+ * - Nyquist mode (qcoll_params.nyquist): by default the DFT index N/2
+ *   (frequency -N/2) is shifted as the cosine mode of the real trigonometric
+ *   interpolant, factor cos(pi (N/2) s_d / L) per axis, so every intermediate
+ *   of Q(f,f) is real; the literal convention is available per plan.
  * - Errors: a qcoll_status; qcoll_last_error() gives a thread-local detail
  *   string.  No exception, abort or exit crosses this interface.
  * - Concurrency: a plan is immutable after creation (except through
@@ -62,7 +63,8 @@ typedef enum {
 typedef enum { QCOLL_FP64 = 0, QCOLL_FP32 = 1 } qcoll_precision;
 
 /* Plan parameters.
- *   N          points per velocity axis; supported: 8, 12, 16, 24, 32, 48.
+ *   N          points per velocity axis; supported: 8, 12, 16, 24, 32, 48, 64
+ *              (64: symmetric or literal VHS plans, no VJP).
  *   L          half-width of the periodic velocity box [-L, L]^3, L > 0.
  *   N_rho      Gauss-Legendre nodes of the radial rule on [0, R],
  *              R = 4L/(3 + sqrt 2) (Appendix: ball truncation); 1..64.
@@ -91,7 +93,18 @@ typedef enum { QCOLL_FP64 = 0, QCOLL_FP32 = 1 } qcoll_precision;
  *              with sigma_i > svd_tol * sigma_1.
  *   svd_tol    relative truncation threshold used when svd_rank == 0.
  *   precision  qcoll_precision.
+ *   nyquist    qcoll_nyquist: how the shift acts on the self-paired DFT index
+ *              N/2 (Appendix: the index set k = -N/2 .. N/2 - 1).  SYMMETRIC
+ *              takes the real interpolant's cosine factor cos(pi (N/2) s_d / L)
+ *              (every intermediate real; the default and the fast path).
+ *              LITERAL takes exp(i pi k s_d / L) at k = -N/2 as printed: the
+ *              shifted copies t1, t2 and the gain are complex and Q is the real
+ *              part.  LITERAL plans run the two-pass schedule with two inverse
+ *              transforms per term; qcoll_vjp, qcoll_eval_bilinear and
+ *              qcoll_dg_collide_svd return ENOTSUP for them, as do VSS kernels.
  */
+typedef enum { QCOLL_NYQ_SYMMETRIC = 0, QCOLL_NYQ_LITERAL = 1 } qcoll_nyquist;
+
 typedef struct {
   int32_t N;
   double L;
@@ -104,6 +117,7 @@ typedef struct {
   int32_t svd_rank;
   double svd_tol;
   int32_t precision;
+  int32_t nyquist;
 } qcoll_params;
 
 /* Plan facts for diagnostics; filled by qcoll_plan_info. */
@@ -224,7 +238,7 @@ qcoll_status qcoll_timing_reset(void);
 qcoll_status qcoll_timing_read(const char *name, double *host_ms, int64_t *host_count);
 qcoll_status qcoll_timing_names(char *host_buf, size_t cap);
 
-/* DG collision term of the weak form (Section 3.4, the collision double sum
+/* DG collision term of the weak form (Section 3.3.1, the collision double sum
  * and its SVD variant):
  *   C[e][m] = sum_r W[m][r] Q( sum_l T[r][l] F[e][l] ),   m < K, r < R,
  * for every element e.  With T the stacked eigenvectors u_{m,r} of the
@@ -239,6 +253,21 @@ size_t qcoll_dg_workspace_bytes(qcoll_plan plan, int64_t n_elem, int32_t K, int3
 qcoll_status qcoll_dg_collide(qcoll_plan plan, int64_t n_elem, int32_t K, int32_t R, const double *T,
                               const double *W, const double *F, double *C, int32_t conserve, void *ws,
                               size_t ws_bytes, void *stream);
+
+/* The collocated form of the same DG collision term (nodal basis on the K
+ * quadrature points of the element, Section 3.3.1 with the K-point rule): T is
+ * the identity and W = diag(w), so
+ *   C[e][m] = w_m Q(F[e][m]),   m < K,
+ * e.g. w_m = J times the Gauss weight of node m.  No contraction runs: F is
+ * evaluated as a batch of n_elem*K items and each item's weight is applied
+ * in the store of the last pass (after the projection when conserve != 0;
+ * the projection is linear).  host_w: HOST [K] finite weights; F, C device
+ * FP64 [n_elem][K][N^3], C must not overlap F.  Workspace from
+ * qcoll_dg_collocated_workspace_bytes. */
+size_t qcoll_dg_collocated_workspace_bytes(qcoll_plan plan, int64_t n_elem, int32_t K);
+qcoll_status qcoll_dg_collide_collocated(qcoll_plan plan, int64_t n_elem, int32_t K, const double *host_w,
+                                         const double *F, double *C, int32_t conserve, void *ws, size_t ws_bytes,
+                                         void *stream);
 
 /* Items per chunk of the eval pipeline (0 = default 64); workspace sizes
  * depend on it.  Results do not. */
@@ -279,6 +308,13 @@ qcoll_status qcoll_group_eval(qcoll_group group, const double *const *f, double 
 qcoll_status qcoll_group_vjp(qcoll_group group, const double *const *f, const double *const *g,
                              double *const *df, double *const *domega, int32_t through_conserve,
                              void *ws, size_t ws_bytes, void *stream, int32_t use_graph);
+/* Autotune every member plan on its own inputs (qcoll_autotune with the
+ * plan's item count; Q entries are overwritten), so that a later captured
+ * graph records the tuned schedules.  Synchronous.  Workspace from
+ * qcoll_group_autotune_workspace_bytes (the largest member's need). */
+size_t qcoll_group_autotune_workspace_bytes(qcoll_group group);
+qcoll_status qcoll_group_autotune(qcoll_group group, const double *const *f, double *const *Q, void *ws,
+                                  size_t ws_bytes, void *stream);
 
 /* The paper's SVD variant of the DG collision term with general factors:
  *   C[e][m] = sum_r W[m][r] Q( sum_l T1[r][l] F[e][l], sum_l T2[r][l] F[e][l] )
@@ -293,7 +329,7 @@ qcoll_status qcoll_dg_collide_svd(qcoll_plan plan, int64_t n_elem, int32_t K, in
 /* 1-D RKDG driver (Section 3): DG in x on the K = P+1 Gauss-Legendre nodes of
  * every element (diagonal mass matrix), the upwind flux of Section 3.2, the
  * collision term of the weak form through the plan, SSP-RK2/RK3 of Section
- * 3.5 and the boundary conditions of Section 3.6.  The walls are normal to x.
+ * 3.4 and the boundary conditions of Section 3.5.  The walls are normal to x.
  *   F, R: device FP64 [n_elem][K][N^3] nodal values (item order of qcoll_eval);
  *   dF_m/dt = (c_x (S F)_m - face terms) / (J w_m) + inv_kn * C_m / (J w_m),
  *   C_m = sum_{l1,l2} H_{m l1 l2} Q(F_l1, F_l2) with H exact (eigen form of the

@@ -1,4 +1,4 @@
-"""DG weak form of the collision term (Section 3.2 and 3.4), FP64.
+"""DG weak form of the collision term (Sections 3.2 and 3.3.1), FP64.
 
 * Nodal basis: Lagrange polynomials on the P+1 Gauss-Legendre nodes of the
   reference element [-1, 1] (1-D), tensor products on quadrilaterals (2-D).

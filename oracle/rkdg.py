@@ -12,14 +12,14 @@ Follows Section 3 in the paper's order:
                     + (1/Kn) C_m,
   with the upwind flux f* (interior trace when c.n >= 0, exterior otherwise) and
   the collision term C_m = sum_{l1,l2} H_{m l1 l2} Q(F_l1, F_l2).
-* Collision term (Section 3.4): ``coll="exact"`` uses the exact triple tensor
+* Collision term (Section 3.3.1): ``coll="exact"`` uses the exact triple tensor
   H = J H_ref through its eigen factors (oracle.dg); ``coll="collocation"``
   uses H from the K-point rule itself, H_{m l1 l2} = J w_m delta delta, so that
   C_m = J w_m Q(F_m).  Optionally each Q is conservation-projected.
 * Velocity space (Section 3.3): the N^3 cell-centred grid; Q from
   oracle.spectral.
-* Time (Section 3.5): SSP-RK2 and SSP-RK3 (and forward Euler).
-* Boundaries (Section 3.6): periodic; fully diffuse wall at (u_w, T_w), where
+* Time (Section 3.4): SSP-RK2 and SSP-RK3 (and forward Euler).
+* Boundaries (Section 3.5): periodic; fully diffuse wall at (u_w, T_w), where
   for (c - u_w).n < 0 the exterior state is n_w exp(-|c - u_w|^2 / T_w) with
   n_w from zero net mass flux through the wall (discrete sums over the grid);
   inflow Maxwellian n (pi T)^{-3/2} exp(-|c - u|^2 / T) for c.n < 0.

@@ -12,6 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqcoll.so")
 
 QCOLL_FP64, QCOLL_FP32 = 0, 1
+QCOLL_NYQ_SYMMETRIC, QCOLL_NYQ_LITERAL = 0, 1
 STATUS = {0: "QCOLL_OK", 1: "QCOLL_EINVAL", 2: "QCOLL_ENOTSUP", 3: "QCOLL_ENOMEM",
           4: "QCOLL_EDEVICE", 5: "QCOLL_EWORKSPACE", 6: "QCOLL_ENONFINITE"}
 
@@ -27,7 +28,7 @@ class Params(ctypes.Structure):
                 ("M", ctypes.c_int32), ("sphere", ctypes.POINTER(ctypes.c_double)),
                 ("omega", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("prefactor", ctypes.c_double), ("svd_rank", ctypes.c_int32),
-                ("svd_tol", ctypes.c_double), ("precision", ctypes.c_int32)]
+                ("svd_tol", ctypes.c_double), ("precision", ctypes.c_int32), ("nyquist", ctypes.c_int32)]
 
 
 class Bc(ctypes.Structure):
@@ -87,6 +88,9 @@ def lib():
             "qcoll_dg_svd_workspace_bytes": ([vp, i64, i32, i32], ctypes.c_size_t),
             "qcoll_dg_collide_svd": ([vp, i64, i32, i32, dp, dp, dp, dp, dp, i32, vp, ctypes.c_size_t, vp], i32),
             "qcoll_dg_workspace_bytes": ([vp, i64, i32, i32], ctypes.c_size_t),
+            "qcoll_dg_collocated_workspace_bytes": ([vp, i64, i32], ctypes.c_size_t),
+            "qcoll_dg_collide_collocated": ([vp, i64, i32, ctypes.POINTER(ctypes.c_double), dp, dp, i32, vp,
+                                             ctypes.c_size_t, vp], i32),
             "qcoll_dg_collide": ([vp, i64, i32, i32, dp, dp, dp, dp, i32, vp, ctypes.c_size_t, vp], i32),
             "qcoll_plan_set_chunk": ([vp, i32], i32),
             "qcoll_autotune_workspace_bytes": ([vp, i64], ctypes.c_size_t),
@@ -99,6 +103,8 @@ def lib():
                                  i32),
             "qcoll_group_vjp": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                 ctypes.POINTER(vp), i32, vp, ctypes.c_size_t, vp, i32], i32),
+            "qcoll_group_autotune_workspace_bytes": ([vp], ctypes.c_size_t),
+            "qcoll_group_autotune": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, ctypes.c_size_t, vp], i32),
             "qcoll_dg1d_create": ([vp, ctypes.POINTER(Dg1dParams), ctypes.POINTER(vp)], i32),
             "qcoll_dg1d_destroy": ([vp], i32),
             "qcoll_dg1d_nodes": ([vp, ctypes.POINTER(ctypes.c_double)], i32),
@@ -126,7 +132,7 @@ def _check(code):
 
 
 def make_params(N, L, N_rho, sphere=None, omega=1.0, prefactor=None, svd_rank=-1, svd_tol=0.0,
-                precision=QCOLL_FP64, alpha=1.0):
+                precision=QCOLL_FP64, alpha=1.0, nyquist="symmetric"):
     """Build a Params struct; sphere is (points [M,3], weights [M]) or None for the built-in M=6 rule.
     Returns (params, keepalive)."""
     keep = None
@@ -151,6 +157,8 @@ def make_params(N, L, N_rho, sphere=None, omega=1.0, prefactor=None, svd_rank=-1
     p.svd_rank = int(svd_rank)
     p.svd_tol = float(svd_tol)
     p.precision = int(precision)
+    p.nyquist = {"symmetric": QCOLL_NYQ_SYMMETRIC, "literal": QCOLL_NYQ_LITERAL}[nyquist] \
+        if isinstance(nyquist, str) else int(nyquist)
     return p, keep
 
 
@@ -182,13 +190,14 @@ class Plan:
     """A plan for one velocity grid and kernel.  See include/qcoll.h."""
 
     def __init__(self, N, L, N_rho, sphere=None, omega=1.0, prefactor=None, svd_rank=-1,
-                 svd_tol=0.0, precision=QCOLL_FP64, device=None, alpha=1.0):
-        """alpha: VSS scattering exponent (1 = VHS; (1, 2] = VSS, full table only)."""
+                 svd_tol=0.0, precision=QCOLL_FP64, device=None, alpha=1.0, nyquist="symmetric"):
+        """alpha: VSS scattering exponent (1 = VHS; (1, 2] = VSS, full table only).
+        nyquist: "symmetric" (default) or "literal" shift at frequency -N/2."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("qcoll needs a ROCm GPU")
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
-        p, keep = make_params(N, L, N_rho, sphere, omega, prefactor, svd_rank, svd_tol, precision, alpha)
+        p, keep = make_params(N, L, N_rho, sphere, omega, prefactor, svd_rank, svd_tol, precision, alpha, nyquist)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(lib().qcoll_plan_create(ctypes.byref(p), ctypes.byref(h)))
@@ -374,6 +383,36 @@ class Plan:
             _keep_for(t, stream)
         return out
 
+    def dg_collide_collocated(self, F, weights, conserve=False, out=None, stream=None):
+        """Collocated DG collision term C[e][m] = w_m Q(F[e][m]) (T = I, W = diag(w)).
+
+        F: float64 [n_elem, K, N, N, N] CUDA tensor; weights: K host floats."""
+        import numpy as np
+        import torch
+        n = self.N
+        if F.dim() != 5 or F.shape[2:] != (n, n, n) or F.dtype != torch.float64 or not F.is_contiguous() \
+                or F.device != self.device:
+            raise ValueError(f"F must be a contiguous float64 tensor [n_elem, K, N, N, N] on {self.device}")
+        E, K = F.shape[0], F.shape[1]
+        w = np.ascontiguousarray(weights, dtype=np.float64).reshape(-1)
+        if w.size != K:
+            raise ValueError("weights must have K entries")
+        if out is None:
+            out = torch.empty_like(F)
+        else:
+            self._check_out(out, "out", F.shape)
+        need = int(lib().qcoll_dg_collocated_workspace_bytes(self._h, E, K))
+        key = ("colloc", torch.cuda.current_stream(self.device).cuda_stream if stream is None else stream.cuda_stream)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        _check(lib().qcoll_dg_collide_collocated(self._h, E, K, w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                 _ptr(F), _ptr(out), int(bool(conserve)), _ptr(ws), ws.numel(),
+                                                 _stream(stream)))
+        _keep_for(ws, stream)
+        return out
+
     def dg_collide_svd(self, F, T1, T2, W, conserve=False, out=None, stream=None):
         """The paper's SVD form: C[e][m] = sum_r W[m][r] Q(T1_r . F[e], T2_r . F[e]) (bilinear Q)."""
         import torch
@@ -500,6 +539,21 @@ class Group:
         _check(lib().qcoll_group_eval(self._h, self._arr(fs), self._arr(Qs), int(bool(conserve)), _ptr(ws),
                                       ws.numel(), _stream(stream), int(bool(use_graph))))
         return Qs
+
+    def autotune(self, fs, Qs=None, stream=None):
+        """Autotune every member plan on its inputs (before the first graph capture)."""
+        import torch
+        if Qs is None:
+            Qs = [torch.empty_like(f) for f in fs]
+        for p, f, q, c in zip(self.plans, fs, Qs, self.counts):
+            if p._check_f(f, "f") != c or p._check_f(q, "Q") != c:
+                raise ValueError("item counts differ from the group's")
+        need = int(lib().qcoll_group_autotune_workspace_bytes(self._h))
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.plans[0].device)
+        _check(lib().qcoll_group_autotune(self._h, self._arr(fs), self._arr(Qs), _ptr(ws), ws.numel(),
+                                          _stream(stream)))
+        for p in self.plans:
+            p._ws = {}
 
     def vjp(self, fs, gs, dfs=None, domegas=None, through_conserve=True, use_graph=True, stream=None):
         import torch

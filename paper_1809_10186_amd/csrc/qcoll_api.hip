@@ -1,6 +1,9 @@
 // C ABI: argument validation, plan lifetime and dispatch.
 #include <cmath>
+#include <cstdarg>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -14,7 +17,28 @@ qcoll_status plan_table(const Plan &p, int which, double *host, size_t n);
 void plan_free(Plan &p);
 
 static thread_local std::string g_err;
-void set_error(const std::string &msg) { g_err = msg; }
+void set_error(const std::string &msg) {
+  g_err = msg;
+  if (log_on()) log("error: %s", msg.c_str());
+}
+
+bool log_on() {
+  static const bool on = [] {
+    const char *e = std::getenv("QCOLL_LOG");
+    return e && *e && std::strcmp(e, "0") != 0;
+  }();
+  return on;
+}
+
+void log(const char *fmt, ...) {
+  if (!log_on()) return;
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  std::fprintf(stderr, "[qcoll] %s\n", buf);
+}
 }  // namespace qcoll
 
 using qcoll::set_error;
@@ -40,7 +64,10 @@ extern "C" {
 int32_t qcoll_version(void) { return 1; }
 
 const char *qcoll_status_str(qcoll_status s) {
-  switch (s) {
+  // C callers may pass any int: read it as one (no load of an out-of-range enum)
+  int v = 0;
+  std::memcpy(&v, &s, sizeof v);
+  switch (v) {
     case QCOLL_OK: return "QCOLL_OK";
     case QCOLL_EINVAL: return "QCOLL_EINVAL";
     case QCOLL_ENOTSUP: return "QCOLL_ENOTSUP";
@@ -57,7 +84,8 @@ const char *qcoll_last_error(void) { return qcoll::g_err.c_str(); }
 qcoll_status qcoll_params_check(const qcoll_params *p) {
   if (!p) return fail(QCOLL_EINVAL, "params is NULL");
   if (!(p->N > 0) || p->N % 2) return fail(QCOLL_EINVAL, "N must be a positive even integer");
-  if (!qcoll::supported_N(p->N)) return fail(QCOLL_ENOTSUP, "N must be one of 8, 12, 16, 24, 32, 48");
+  if (!qcoll::supported_N(p->N)) return fail(QCOLL_ENOTSUP, "N must be one of 8, 12, 16, 24, 32, 48, 64");
+  if (p->N == 64 && p->alpha != 1.0) return fail(QCOLL_ENOTSUP, "VSS kernels support N <= 48");
   if (!(p->L > 0.0) || !std::isfinite(p->L)) return fail(QCOLL_EINVAL, "L must be finite and > 0");
   if (p->N_rho < 1) return fail(QCOLL_EINVAL, "N_rho must be >= 1");
   if (p->N_rho > 64) return fail(QCOLL_ENOTSUP, "N_rho must be <= 64");
@@ -67,6 +95,10 @@ qcoll_status qcoll_params_check(const qcoll_params *p) {
     return fail(QCOLL_ENOTSUP, "VSS plans keep the full kernel-mode table (svd_rank < 0)");
   if (std::isinf(p->prefactor)) return fail(QCOLL_EINVAL, "prefactor must be finite (or NaN/<= 0 for the VHS constant)");
   if (p->precision != QCOLL_FP64 && p->precision != QCOLL_FP32) return fail(QCOLL_EINVAL, "unknown precision");
+  if (p->nyquist != QCOLL_NYQ_SYMMETRIC && p->nyquist != QCOLL_NYQ_LITERAL)
+    return fail(QCOLL_EINVAL, "nyquist must be QCOLL_NYQ_SYMMETRIC or QCOLL_NYQ_LITERAL");
+  if (p->nyquist == QCOLL_NYQ_LITERAL && p->alpha != 1.0)
+    return fail(QCOLL_ENOTSUP, "the literal Nyquist convention needs a VHS kernel (alpha = 1)");
   if (p->svd_rank == 0 && !(p->svd_tol > 0.0 && p->svd_tol < 1.0))
     return fail(QCOLL_EINVAL, "svd_rank == 0 needs 0 < svd_tol < 1");
   if (p->svd_rank > p->N_rho) return fail(QCOLL_EINVAL, "svd_rank must be <= N_rho");
@@ -101,6 +133,12 @@ qcoll_status qcoll_plan_create(const qcoll_params *prm, qcoll_plan *out) {
     return st;
   }
   *out = h;
+  const auto &p = h->p;
+  qcoll::log("plan %p: N=%d L=%g N_rho=%d M=%d omega=%g alpha=%g b=%.10g rank=%d (sigma %.3e..%.3e) %s %s "
+             "nyquist=%s device=%d",
+             static_cast<void *>(h), p.N, p.L, p.N_rho, p.M, p.omega, p.vss, p.b, p.rank, p.sigma_max,
+             p.sigma_min_kept, p.precision == QCOLL_FP32 ? "fp32" : "fp64", p.truncated ? "truncated" : "full",
+             p.literal ? "literal" : "symmetric", p.device);
   return QCOLL_OK;
 }
 
@@ -155,11 +193,13 @@ qcoll_status qcoll_plan_set_omega(qcoll_plan plan, double omega) {
 qcoll_status qcoll_plan_set_schedule(qcoll_plan plan, int32_t schedule) {
   if (!plan) return fail(QCOLL_EINVAL, "plan is NULL");
   if (schedule < 0 || schedule > 2) return fail(QCOLL_EINVAL, "schedule must be 0, 1 or 2");
-  if (schedule == 2 && !qcoll::onchip_schedule_supported(plan->p.N, plan->p.precision))
-    return fail(QCOLL_ENOTSUP, "the on-chip gain kernels need FP32 with N <= 32 or FP64 with N = 16");
+  if (schedule == 2 && !qcoll::onchip_schedule_supported(plan->p))
+    return fail(QCOLL_ENOTSUP, "the on-chip gain kernels need FP32 with N <= 32 or FP64 with N = 16, "
+                               "and the symmetric Nyquist convention");
   plan->p.schedule = schedule;
   plan->p.schedule_user = schedule;
   ++plan->p.gen;
+  qcoll::log("plan %p: schedule %d", static_cast<void *>(plan), schedule);
   return QCOLL_OK;
 }
 
@@ -191,6 +231,7 @@ qcoll_status qcoll_eval_bilinear(qcoll_plan plan, int64_t batch, const double *f
   if (batch == 0) return QCOLL_OK;
   if (!f || !g || !Q) return fail(QCOLL_EINVAL, "f, g and Q must be non-NULL");
   if (plan->p.is_vss()) return fail(QCOLL_ENOTSUP, "the bilinear Q needs a VHS plan (alpha = 1)");
+  if (plan->p.literal) return fail(QCOLL_ENOTSUP, "the bilinear Q needs the symmetric Nyquist convention");
   const long n3 = plan->p.n3();
   auto overlap = [&](const void *a) {
     return a < (const void *)(Q + batch * n3) && (const void *)Q < (const void *)((const double *)a + batch * n3);
@@ -233,6 +274,8 @@ qcoll_status qcoll_vjp(qcoll_plan plan, int64_t batch, const double *f, const do
   if (batch == 0) return QCOLL_OK;
   if (!f || !g) return fail(QCOLL_EINVAL, "f and g must be non-NULL");
   if (plan->p.is_vss()) return fail(QCOLL_ENOTSUP, "the VJP needs a VHS plan (alpha = 1)");
+  if (plan->p.literal) return fail(QCOLL_ENOTSUP, "the VJP needs the symmetric Nyquist convention");
+  if (plan->p.N > 48) return fail(QCOLL_ENOTSUP, "the VJP supports N <= 48");
   if (!df && !domega) return QCOLL_OK;
   if (domega && plan->p.truncated)
     return fail(QCOLL_ENOTSUP, "the omega gradient needs an untruncated plan (svd_rank < 0)");
@@ -284,6 +327,60 @@ qcoll_status qcoll_dg_collide(qcoll_plan plan, int64_t n_elem, int32_t K, int32_
   return qcoll::launch_dg_contract(W, Qd, C, n_elem, K, R, long(n3), s);
 }
 
+size_t qcoll_dg_collocated_workspace_bytes(qcoll_plan plan, int64_t n_elem, int32_t K) {
+  if (!plan || n_elem < 0 || K < 1 || K > 64) return 0;
+  return 512 + qcoll::make_layout(plan->p, n_elem * K, 0).total;
+}
+
+namespace {
+struct Weights {
+  double w[64];
+};
+
+// the K collocation weights into device memory (kernel argument -> workspace)
+__global__ void k_fill_weights(Weights wt, int K, double *out) {
+#pragma unroll
+  for (int k = 0; k < 64; ++k)
+    if (k < K && int(threadIdx.x) == k) out[k] = wt.w[k];
+}
+}  // namespace
+
+qcoll_status qcoll_dg_collide_collocated(qcoll_plan plan, int64_t n_elem, int32_t K, const double *host_w,
+                                         const double *F, double *C, int32_t conserve, void *ws, size_t ws_bytes,
+                                         void *stream) {
+  if (!plan) return fail(QCOLL_EINVAL, "plan is NULL");
+  if (n_elem < 0) return fail(QCOLL_EINVAL, "n_elem must be >= 0");
+  if (K < 1 || K > 64) return fail(QCOLL_EINVAL, "need 1 <= K <= 64");
+  if (n_elem == 0) return QCOLL_OK;
+  if (!host_w || !F || !C) return fail(QCOLL_EINVAL, "host_w, F and C must be non-NULL");
+  const int64_t items = n_elem * K;
+  if (items > 0x7fffffff) return fail(QCOLL_EINVAL, "n_elem * K too large");
+  const long n3 = plan->p.n3();
+  if ((const void *)F < (const void *)(C + items * n3) && (const void *)C < (const void *)(F + items * n3))
+    return fail(QCOLL_EINVAL, "C must not overlap F");
+  for (int k = 0; k < K; ++k)
+    if (!std::isfinite(host_w[k])) return fail(QCOLL_EINVAL, "collocation weights must be finite");
+  if (!ws || ws_bytes < qcoll_dg_collocated_workspace_bytes(plan, n_elem, K))
+    return fail(QCOLL_EWORKSPACE, "workspace missing or smaller than qcoll_dg_collocated_workspace_bytes");
+  qcoll_status st = check_device(plan->p);
+  if (st != QCOLL_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double *wd = static_cast<double *>(ws);
+  Weights wt{};
+  for (int k = 0; k < K; ++k) wt.w[k] = host_w[k];
+  hipLaunchKernelGGL(k_fill_weights, dim3(1), dim3(64), 0, s, wt, int(K), wd);
+  if (hipGetLastError() != hipSuccess) return fail(QCOLL_EDEVICE, "weight fill launch failed");
+  void *ews = static_cast<char *>(ws) + 512;
+  const qcoll::Layout lay = qcoll::make_layout(plan->p, items, 0);
+  // Q of every (element, node) straight from F (T = I: no contraction), stored
+  // scaled by its node weight (W diagonal), or projected first and scaled by
+  // the projection (it is linear, so it commutes with the weight)
+  if ((st = qcoll::launch_eval(plan->p, items, F, C, ews, lay, s, conserve ? nullptr : wd, K)) != QCOLL_OK)
+    return st;
+  if (conserve && (st = qcoll::launch_conserve(plan->p, items, C, nullptr, s, wd, K)) != QCOLL_OK) return st;
+  return QCOLL_OK;
+}
+
 size_t qcoll_dg_svd_workspace_bytes(qcoll_plan plan, int64_t n_elem, int32_t K, int32_t R) {
   if (!plan || n_elem < 0 || K < 1 || R < 1) return 0;
   const size_t n3 = size_t(plan->p.n3());
@@ -301,6 +398,7 @@ qcoll_status qcoll_dg_collide_svd(qcoll_plan plan, int64_t n_elem, int32_t K, in
   if (n_elem == 0) return QCOLL_OK;
   if (!T1 || !T2 || !W || !F || !C) return fail(QCOLL_EINVAL, "T1, T2, W, F and C must be non-NULL");
   if (plan->p.is_vss()) return fail(QCOLL_ENOTSUP, "the bilinear Q needs a VHS plan (alpha = 1)");
+  if (plan->p.literal) return fail(QCOLL_ENOTSUP, "the bilinear Q needs the symmetric Nyquist convention");
   const size_t n3 = size_t(plan->p.n3());
   const size_t terms = size_t(n_elem) * R;
   if (terms > size_t(0x7fffffff)) return fail(QCOLL_EINVAL, "n_elem * R too large");

@@ -1,4 +1,4 @@
-// DG collision term of the weak form (Section 3.4):
+// DG collision term of the weak form (Section 3.3.1):
 //   C[e][m] = sum_r W[m][r] Q( sum_l T[r][l] F[e][l] ),
 // which covers the paper's SVD (eigen) variant (T = stacked eigenvectors of the
 // triple tensor H_m, W = their eigenvalues) and the quadrature form (T = basis

@@ -1,7 +1,7 @@
 // 1-D RKDG driver (Section 3): nodal DG in x on K = P+1 Gauss-Legendre nodes
 // per element, upwind flux (Section 3.2), the weak-form collision term through
-// the plan (Section 3.4), SSP-RK2/RK3 (Section 3.5), periodic / fully diffuse
-// wall / inflow ends (Section 3.6).
+// the plan (Section 3.3.1), SSP-RK2/RK3 (Section 3.4), periodic / fully diffuse
+// wall / inflow ends (Section 3.5).
 //
 // State F [I][K][N^3] FP64.  With the K-point rule the mass matrix is
 // J w_m delta_ml, so per node
@@ -435,7 +435,7 @@ qcoll_status qcoll_dg1d_create(qcoll_plan plan, const qcoll_dg1d_params *prm, qc
     delete d;
     return st;
   }
-  // exact triple tensor of the reference element and its eigen factors (Section 3.4)
+  // exact triple tensor of the reference element and its eigen factors (Section 3.3.1)
   d->R = K;
   if (prm->coll_form == 1) {
     std::vector<double> xq, wqq;
@@ -550,7 +550,7 @@ qcoll_status qcoll_dg1d_step(qcoll_dg1d d, double *F, double dt, int32_t rk, voi
   qcoll_status s;
   if ((s = dg1d_rhs(d, F, Rb, w, l, st)) != QCOLL_OK) return s;
   if (rk == 1) return axpby3(F, F, 1.0, Rb, dt, nullptr, 0.0, n, st);
-  // SSP-RK2 / SSP-RK3 (Section 3.5)
+  // SSP-RK2 / SSP-RK3 (Section 3.4)
   if ((s = axpby3(v1, F, 1.0, Rb, dt, nullptr, 0.0, n, st)) != QCOLL_OK) return s;
   if ((s = dg1d_rhs(d, v1, Rb, w, l, st)) != QCOLL_OK) return s;
   if (rk == 2) return axpby3(F, F, 0.5, v1, 0.5, Rb, 0.5 * dt, n, st);

@@ -213,7 +213,7 @@ static qcoll_status launch_q64(const Plan &p, const cplx<double> *H, double *A, 
 bool gain_q64_supported(int N, int precision) { return precision == QCOLL_FP64 && N == 16; }
 
 bool use_gain_q64(const Plan &p) {
-  return p.schedule != 1 && !p.is_vss() && gain_q64_supported(p.N, p.precision);
+  return p.schedule != 1 && !p.is_vss() && !p.literal && gain_q64_supported(p.N, p.precision);
 }
 
 qcoll_status launch_gain_q64(const Plan &p, const void *H, double *A, long nbp, hipStream_t st) {

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cerrno>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -166,6 +167,8 @@ qcoll_status run(qcoll_group g, int32_t op, const double *const *a, const double
   c.st = st;
   c.exec = exec;
   g->cache.push_back(c);
+  qcoll::log("group %p: captured graph %zu for op %d (%zu plans)", static_cast<void *>(g), g->cache.size(), op,
+             g->plans.size());
   if (hipGraphLaunch(exec, st) != hipSuccess) return gfail(QCOLL_EDEVICE, "hipGraphLaunch failed");
   return QCOLL_OK;
 }
@@ -239,7 +242,9 @@ qcoll_status qcoll_group_vjp(qcoll_group g, const double *const *f, const double
                              void *stream, int32_t use_graph) {
   if (g)
     for (size_t i = 0; i < g->plans.size(); ++i)
-      if (g->plans[i]->p.is_vss()) return gfail(QCOLL_ENOTSUP, "the VJP needs VHS plans (alpha = 1)");
+      if (g->plans[i]->p.is_vss() || g->plans[i]->p.literal || g->plans[i]->p.N > 48)
+        return gfail(QCOLL_ENOTSUP,
+                     "the VJP needs VHS plans (alpha = 1) with the symmetric Nyquist convention and N <= 48");
   if (g && domega)
     for (size_t i = 0; i < g->plans.size(); ++i)
       if (domega[i] && g->plans[i]->p.truncated)
@@ -256,6 +261,7 @@ qcoll_status qcoll_plan_set_chunk(qcoll_plan plan, int32_t items) {
   if (items < 0 || items > 65536) return gfail(QCOLL_EINVAL, "chunk must be 0..65536");
   plan->p.chunk = items;
   ++plan->p.gen;
+  qcoll::log("plan %p: chunk %d", static_cast<void *>(plan), items);
   return QCOLL_OK;
 }
 
@@ -278,7 +284,7 @@ size_t qcoll_autotune_workspace_bytes(qcoll_plan plan, int64_t batch) {
   size_t mx = 0;
   for (int sch : {1, 2})
     for (int ck : tune_chunks(batch)) {
-      if (sch == 2 && !qcoll::onchip_schedule_supported(p.N, p.precision)) continue;
+      if (sch == 2 && !qcoll::onchip_schedule_supported(p)) continue;
       p.schedule = sch;
       p.chunk = ck;
       mx = std::max(mx, qcoll::make_layout(p, batch, 0).total);
@@ -309,12 +315,21 @@ qcoll_status qcoll_autotune(qcoll_plan plan, int64_t batch, const double *f, dou
     while (std::getline(in, line)) {
       const size_t bar = line.find('|');
       if (bar == std::string::npos || line.substr(0, bar) != key) continue;
-      int sch = 0, ck = 0;
-      if (std::sscanf(line.c_str() + bar + 1, "%d %d", &sch, &ck) == 2 &&
-          (sch != 2 || qcoll::onchip_schedule_supported(p.N, p.precision))) {
+      // "<schedule> <chunk> [ms]": schedule 1 or 2, chunk 1..65536; anything
+      // else (garbage, out-of-range numbers) is skipped
+      const char *c0 = line.c_str() + bar + 1;
+      char *e1 = nullptr, *e2 = nullptr;
+      errno = 0;
+      const long sch_l = std::strtol(c0, &e1, 10);
+      const long ck_l = (e1 != c0) ? std::strtol(e1, &e2, 10) : 0;
+      const bool parsed = errno == 0 && e1 != c0 && e2 && e2 != e1 && (sch_l == 1 || sch_l == 2) && ck_l >= 1 &&
+                          ck_l <= 65536;
+      const int sch = int(sch_l), ck = int(ck_l);
+      if (parsed && (sch != 2 || qcoll::onchip_schedule_supported(p))) {
         p.schedule = sch;
         p.chunk = ck;
         ++p.gen;
+        qcoll::log("autotune %s: cached schedule %d chunk %d (%s)", key.c_str(), sch, ck, cache);
         if (host_schedule) *host_schedule = sch;
         if (host_chunk) *host_chunk = ck;
         return QCOLL_OK;
@@ -332,7 +347,7 @@ qcoll_status qcoll_autotune(qcoll_plan plan, int64_t batch, const double *f, dou
   qcoll_status rc = QCOLL_OK;
   for (int sch : {2, 1})
     for (int ck : tune_chunks(batch)) {
-      if (sch == 2 && !qcoll::onchip_schedule_supported(p.N, p.precision)) continue;
+      if (sch == 2 && !qcoll::onchip_schedule_supported(p)) continue;
       p.schedule = sch;
       p.chunk = ck;
       const qcoll::Layout lay = qcoll::make_layout(p, batch, 0);
@@ -364,11 +379,35 @@ qcoll_status qcoll_autotune(qcoll_plan plan, int64_t batch, const double *f, dou
   if (rc != QCOLL_OK) return rc;
   p.schedule = bs;
   p.chunk = bc;
+  qcoll::log("autotune %s: schedule %d chunk %d, %.3f ms", key.c_str(), bs, bc, best);
   if (host_schedule) *host_schedule = bs;
   if (host_chunk) *host_chunk = bc;
   if (cache) {
     std::ofstream outf(cache, std::ios::app);
     outf << key << "|" << bs << " " << bc << " " << best << "\n";
+  }
+  return QCOLL_OK;
+}
+
+size_t qcoll_group_autotune_workspace_bytes(qcoll_group g) {
+  if (!g) return 0;
+  size_t mx = 0;
+  for (size_t i = 0; i < g->plans.size(); ++i)
+    if (g->counts[i] > 0) mx = std::max(mx, qcoll_autotune_workspace_bytes(g->plans[i], g->counts[i]));
+  return mx;
+}
+
+qcoll_status qcoll_group_autotune(qcoll_group g, const double *const *f, double *const *Q, void *ws, size_t ws_bytes,
+                                  void *stream) {
+  if (!g || !f || !Q) return gfail(QCOLL_EINVAL, "NULL argument");
+  if (!ws || ws_bytes < qcoll_group_autotune_workspace_bytes(g))
+    return gfail(QCOLL_EWORKSPACE, "workspace smaller than qcoll_group_autotune_workspace_bytes");
+  for (size_t i = 0; i < g->plans.size(); ++i) {
+    if (g->counts[i] == 0) continue;
+    if (!f[i] || !Q[i]) return gfail(QCOLL_EINVAL, "NULL array for a plan with items");
+    const qcoll_status rc = qcoll_autotune(g->plans[i], g->counts[i], f[i], Q[i], ws, ws_bytes, stream, nullptr,
+                                           nullptr);
+    if (rc != QCOLL_OK) return rc;
   }
   return QCOLL_OK;
 }

@@ -11,6 +11,11 @@
 namespace qcoll {
 
 void set_error(const std::string &msg);
+// Diagnostics on stderr when the environment variable QCOLL_LOG is set to a
+// non-empty value other than "0" (read once): plan creation, schedule and
+// chunk choices, autotuner results, group graph captures, argument errors.
+bool log_on();
+void log(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
 
 struct Plan {
   int device = 0;
@@ -18,6 +23,7 @@ struct Plan {
   int nv = 0;                    // rows of V / U the kernels use (rank, or N_rho when the mix saves nothing)
   double L = 0, R = 0, omega = 0, b = 0;
   double vss = 1.0;              // VSS scattering exponent alpha (1: VHS, sigma-independent kernel modes)
+  bool literal = false;          // literal Nyquist convention: complex shift factor at frequency -N/2
   bool b_follows_omega = true;
   bool truncated = false;        // SVD truncation requested (any svd_rank >= 0)
   bool mix_identity = true;      // B_s = A_s (no SVD rotation)
@@ -35,6 +41,8 @@ struct Plan {
   void *phase = nullptr;   // [N_rho*M][3][N] complex: per-axis shift factors b_d(n)
   void *wq = nullptr;      // [M] half-sphere weights
   void *V = nullptr;       // [2*npair][N^3] real: spectral factors of the gain / N^3 (zero-padded row)
+  double *V64 = nullptr;   // FP32 plans: the same rows in FP64 (two-pass low-rank stage); FP64 plans: NULL, V is FP64
+  const double *v64() const { return precision == QCOLL_FP32 ? V64 : static_cast<const double *>(V); }
   void *lam = nullptr;     // [N^3] loss weights / N^3, always FP64
   void *alpha_eff = nullptr;  // [N_rho][N^3] effective gain weights sum_s U_sp V_s / N^3 (fused schedule)
   void *alpha_pq = nullptr;   // VSS: [N_rho][M][(N/2+1) N^2] gain weights 2 w_p w_q F(k, rho_p, sigma_q) / N^3,
@@ -68,13 +76,17 @@ struct Layout {
   size_t total = 0;
 };
 
-Layout make_layout(const Plan &p, int64_t batch, int op);
+// chunk > 0 overrides the plan's items per eval chunk (op 0 and 2)
+Layout make_layout(const Plan &p, int64_t batch, int op, long chunk = 0);
 
+// isc: optional device array of K per-item weights; item i of the call is
+// stored scaled by isc[i % K] (the collocated DG weak form)
 qcoll_status launch_eval(const Plan &p, int64_t batch, const double *f, double *Q, void *ws,
-                         const Layout &lay, hipStream_t st);
+                         const Layout &lay, hipStream_t st, const double *isc = nullptr, int K = 0);
 qcoll_status launch_eval2(const Plan &p, int64_t batch, const double *f, const double *g, double *Q, void *ws,
                           const Layout &lay, hipStream_t st);
-qcoll_status launch_conserve(const Plan &p, int64_t batch, double *Q, double *mom, hipStream_t st);
+qcoll_status launch_conserve(const Plan &p, int64_t batch, double *Q, double *mom, hipStream_t st,
+                             const double *isc = nullptr, int K = 0);
 qcoll_status launch_moments(const Plan &p, int64_t batch, const double *f, double *out,
                             hipStream_t st);
 qcoll_status launch_vjp(const Plan &p, int64_t batch, const double *f, const double *g,
@@ -95,6 +107,9 @@ qcoll_status launch_gain_q64(const Plan &p, const void *H, double *A, long nbp, 
 // schedule 2 exists for this grid and precision (FP32 fused kernel or FP64 on-chip gain)
 inline bool onchip_schedule_supported(int N, int precision) {
   return fused_gain_supported(N, precision) || gain_q64_supported(N, precision);
+}
+inline bool onchip_schedule_supported(const Plan &p) {
+  return !p.literal && onchip_schedule_supported(p.N, p.precision);
 }
 // sum over the N_rho per-node spectra of each item (FP32 complex, float4 units)
 void launch_sum_nodes(const void *W, void *out, long nitems, int Nr, long n_in, long n_out, hipStream_t st);

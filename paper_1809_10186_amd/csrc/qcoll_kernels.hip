@@ -14,6 +14,16 @@
 
 namespace qcoll {
 
+// complex input in T widened to U (the literal convention's low-rank stage)
+template <typename T, int N, typename U>
+struct SrcCplxWide {
+  const C<T> *in;
+  __device__ C<U> operator()(long g, int r, int c) const {
+    const C<T> v = in[(g * N + r) * N + c];
+    return C<U>{U(v.re), U(v.im)};
+  }
+};
+
 // hot loop, pencil pass: for each (b, p) and pencil (j2, j3), inverse
 // transform along the first axis for every q and accumulate
 // A_p += w_q (u_re^2 - u_im^2)  (= w_q t1 t2 with t1 = re - im, t2 = re + im).
@@ -179,12 +189,15 @@ static void launch_mix(const T *A, const T *U, T *B, long nitems, int S, int Nr,
   }
 }
 
-// low-rank stage, slab pass: slab g = (b*npair + s)*N + j1, Z = B[2s] + i B[2s+1]
-template <typename T, int N>
+// low-rank stage, slab pass: slab g = (b*npair + s)*N + j1, Z = B[2s] + i B[2s+1];
+// the rows are read in the working precision T and transformed in U (FP64:
+// the forward transform of the gain accumulators is where FP32 rounding costs
+// most once gain and loss cancel)
+template <typename T, int N, typename U = T>
 struct SrcPair {
   const T *B;
   int S, npair;
-  __device__ C<T> operator()(long g, int r, int c) const {
+  __device__ C<U> operator()(long g, int r, int c) const {
     constexpr long n3 = long(N) * N * N;
     const long t = g / N;
     const int j1 = int(g % N);
@@ -193,30 +206,37 @@ struct SrcPair {
     const long o = (long(j1) * N + r) * N + c;
     const T re = B[(b * S + 2 * s) * n3 + o];
     const T im = (2 * s + 1 < S) ? B[(b * S + 2 * s + 1) * n3 + o] : T(0);
-    return C<T>{re, im};
+    return C<U>{U(re), U(im)};
   }
 };
 
 // low-rank stage, pencil pass: forward along the first axis for each pair s,
 // accumulating T += (V_2s - i V_2s+1) Z^_s (V already carries 1/N^3).
 // With Z = B_2s + i B_2s+1 and V real and even, Re ifft(T) = sum_s C_s B_s.
+// The slab pass before it runs in FP64 in both precisions and leaves FP64
+// volumes W; this pass transforms in the working precision T and stores the
+// gain spectrum in FP64.  (Gain and loss cancel by up to two orders of
+// magnitude in Q: an FP32 gain spectrum and inverse transform cost about 2e-5
+// of ||Q||, an FP32 two-axis forward transform of the accumulators about half
+// of that; the remaining FP32 axis and sums cost a few 1e-6 and keep this
+// pass's registers within two waves per SIMD at N = 48.)
 template <typename T, int N>
 struct OpLowRank {
-  const C<T> *W;
+  const C<double> *W;
   const T *V;
-  C<T> *TA;
+  C<double> *TA;
   int npair;
   __device__ void operator()(long b, int r) const {
     constexpr long n2 = long(N) * N, n3 = n2 * N;
     T tr[N], ti[N];
     static_for<0, N>([&](auto k) { tr[decltype(k)::value] = T(0); ti[decltype(k)::value] = T(0); });
     for (int s = 0; s < npair; ++s) {
-      const C<T> *w = W + (b * npair + s) * n3 + r;
+      const C<double> *w = W + (b * npair + s) * n3 + r;
       T xr[N], xi[N];
       static_for<0, N>([&](auto k) {
-        const C<T> e = w[decltype(k)::value * n2];
-        xr[decltype(k)::value] = e.re;
-        xi[decltype(k)::value] = e.im;
+        const C<double> e = w[decltype(k)::value * n2];
+        xr[decltype(k)::value] = T(e.re);
+        xi[decltype(k)::value] = T(e.im);
       });
       fft_reg<N, -1, T>(xr, xi);
       const T *v0 = V + (2 * s) * n3 + r;
@@ -229,8 +249,10 @@ struct OpLowRank {
         ti[kk] += a * xi[kk] - c * xr[kk];
       });
     }
-    C<T> *o = TA + b * n3 + r;
-    static_for<0, N>([&](auto k) { o[decltype(k)::value * n2] = C<T>{tr[decltype(k)::value], ti[decltype(k)::value]}; });
+    C<double> *o = TA + b * n3 + r;
+    static_for<0, N>([&](auto k) {
+      o[decltype(k)::value * n2] = C<double>{double(tr[decltype(k)::value]), double(ti[decltype(k)::value])};
+    });
   }
 };
 
@@ -256,6 +278,30 @@ __global__ __launch_bounds__(256) void k_sum_nodes(const float4 *__restrict__ W,
     acc.w += v.w;
   }
   out[b * n_out + o] = acc;
+}
+
+// the same node sum of FP32 half spectra, accumulated and stored in FP64 (two
+// complex values per lane: one 16-byte load per node, two 16-byte stores), so
+// that the gain spectrum and its inverse transform stay in FP64
+__global__ __launch_bounds__(256) void k_sum_nodes_wide(const float4 *__restrict__ W, double2 *__restrict__ out,
+                                                        long nitems, int Nr, long n_in, long n_out) {
+  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nitems * n_in) return;
+  const long b = i / n_in, o = i % n_in;
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  const f4v *w = reinterpret_cast<const f4v *>(W + b * Nr * n_in + o);
+  double ax = 0.0, ay = 0.0, az = 0.0, aw = 0.0;
+#pragma unroll 8
+  for (int p = 0; p < Nr; ++p) {
+    const f4v v = __builtin_nontemporal_load(w + p * n_in);
+    ax += double(v.x);
+    ay += double(v.y);
+    az += double(v.z);
+    aw += double(v.w);
+  }
+  double2 *d = out + 2 * (b * n_out + o);
+  d[0] = make_double2(ax, ay);
+  d[1] = make_double2(az, aw);
 }
 
 void launch_sum_nodes(const void *W, void *out, long nitems, int Nr, long n_in, long n_out, hipStream_t st) {
@@ -313,12 +359,17 @@ struct SrcLossHalf {
 
 // final pencil pass: inverse along the first axis of the gain accumulator (T)
 // and of the loss spectrum (FP64), then Q = Re(gain) - f * Re(loss) in FP64.
+// With isc set, item b0 + b of the call is scaled by isc[(b0 + b) % K] (the
+// collocation weights of the DG weak form, folded into this store).
 template <typename T, int N>
 struct OpAssemble {
   const C<T> *TA;
   const C<double> *LH;
   const double *f;
   double *Q;
+  const double *isc;
+  int K;
+  long b0;
   __device__ void operator()(long b, int r) const {
     constexpr long n2 = long(N) * N, n3 = n2 * N;
     double out[N];
@@ -348,8 +399,9 @@ struct OpAssemble {
         out[jj] -= fb[jj * n2] * lr[jj];
       });
     }
+    const double sc = isc ? isc[(b0 + b) % K] : 1.0;
     double *qb = Q + b * n3 + r;
-    static_for<0, N>([&](auto j) { qb[decltype(j)::value * n2] = out[decltype(j)::value]; });
+    static_for<0, N>([&](auto j) { qb[decltype(j)::value * n2] = sc * out[decltype(j)::value]; });
   }
 };
 
@@ -362,6 +414,9 @@ struct OpAssembleHalf {
   const C<double> *LH;
   const double *f;
   double *Q;
+  const double *isc;
+  int K;
+  long b0;
   __device__ void operator()(long b, int r) const {
     constexpr long n2 = long(N) * N, n3 = n2 * N;
     constexpr int H1 = N / 2 + 1;
@@ -400,8 +455,9 @@ struct OpAssembleHalf {
         out[jj] -= fb[jj * n2] * lr[jj];
       });
     }
+    const double sc = isc ? isc[(b0 + b) % K] : 1.0;
     double *qb = Q + b * n3 + r;
-    static_for<0, N>([&](auto j) { qb[decltype(j)::value * n2] = out[decltype(j)::value]; });
+    static_for<0, N>([&](auto j) { qb[decltype(j)::value * n2] = sc * out[decltype(j)::value]; });
   }
 };
 
@@ -526,6 +582,113 @@ __global__ __launch_bounds__(256) void k_vss_acc_add(C<T> *W, const C<T> *Wp, lo
 }
 
 // ----------------------------------------------------------------------------
+// Literal Nyquist convention: the shift factor at frequency -N/2 is the complex
+// exp(i pi k s / L), so beta_s X is no longer Hermitian and the shifted copies
+// t1 = ifft(beta_s X), t2 = ifft(conj(beta_s) X) are complex.  With
+// a = ifft(Re(beta_s) X) and b = ifft(Im(beta_s) X) (each complex now),
+// t1 t2 = (a + i b)(a - i b) = a a + b b, the Appendix's cos/sin form, so each
+// term takes two inverse transforms and a complex product; the gain
+// accumulators A_p and the low-rank stage are complex, and Q = Re(Q+ - Q-).
+
+// slab pass: H times Re(beta_s) (IM = false) or Im(beta_s) (IM = true), with
+// beta_s = b1 b2 b3 formed from b1 b3 once per lane and column (as SrcShift)
+template <typename T, int N, bool IM>
+struct SrcShiftPart {
+  const C<T> *H;
+  const C<T> *phase;
+  long bp0;
+  int M, Nr;
+  T scale;
+  __device__ C<T> operator()(long g, int r, int c) const {
+    const long t = g / N;
+    const int k1 = int(g % N);
+    const long bp = bp0 + t / M;
+    const int q = int(t % M);
+    const long b = bp / Nr;
+    const int p = int(bp % Nr);
+    const C<T> *ph = phase + size_t(p * M + q) * 3 * N;
+    const C<T> b1 = ph[k1], b2 = ph[N + r], b3 = ph[2 * N + c];
+    const T x13 = (b1.re * b3.re - b1.im * b3.im) * scale, y13 = (b1.re * b3.im + b1.im * b3.re) * scale;
+    const T m = IM ? (b2.re * y13 + b2.im * x13) : (b2.re * x13 - b2.im * y13);
+    const C<T> h = H[((b * N + k1) * N + r) * N + c];
+    return C<T>{h.re * m, h.im * m};
+  }
+};
+
+// pencil pass: inverse along axis 1 of the a and b volumes of every q (one
+// pencil held at a time), A_p += w_q (a a + b b), complex A_p stored
+template <typename T, int N>
+struct OpGainAccLit {
+  const C<T> *Ya, *Yb;
+  const T *wq;
+  C<T> *A;
+  long bp0;
+  int M;
+  __device__ void operator()(long bpl, int r) const {
+    constexpr long n2 = long(N) * N, n3 = n2 * N;
+    T accr[N], acci[N];
+    static_for<0, N>([&](auto j) { accr[decltype(j)::value] = T(0); acci[decltype(j)::value] = T(0); });
+    for (int q = 0; q < M; ++q) {
+      const T w = wq[q];
+      for (int part = 0; part < 2; ++part) {
+        const C<T> *y = (part ? Yb : Ya) + (bpl * M + q) * n3 + r;
+        T xr[N], xi[N];
+        static_for<0, N>([&](auto k) {
+          const C<T> v = y[decltype(k)::value * n2];
+          xr[decltype(k)::value] = v.re;
+          xi[decltype(k)::value] = v.im;
+        });
+        fft_reg<N, +1, T>(xr, xi);
+        static_for<0, N>([&](auto j) {
+          constexpr int jj = decltype(j)::value;
+          accr[jj] += w * (xr[jj] * xr[jj] - xi[jj] * xi[jj]);
+          acci[jj] += T(2) * w * (xr[jj] * xi[jj]);
+        });
+      }
+    }
+    C<T> *a = A + (bp0 + bpl) * n3 + r;
+    static_for<0, N>([&](auto j) { a[decltype(j)::value * n2] = C<T>{accr[decltype(j)::value], acci[decltype(j)::value]}; });
+  }
+};
+
+// low-rank stage for complex accumulators: forward along axis 1 of each of
+// the S complex volumes B_s of an item (after the forward slab pass), times
+// the real weights V_s (already / N^3), summed into the FP64 gain spectrum
+template <typename T, int N>
+struct OpLowRankC {
+  const C<T> *W;
+  const T *V;
+  C<double> *TA;
+  int S;
+  __device__ void operator()(long b, int r) const {
+    constexpr long n2 = long(N) * N, n3 = n2 * N;
+    double tr[N], ti[N];
+    static_for<0, N>([&](auto k) { tr[decltype(k)::value] = 0.0; ti[decltype(k)::value] = 0.0; });
+    for (int s = 0; s < S; ++s) {
+      const C<T> *w = W + (b * S + s) * n3 + r;
+      T xr[N], xi[N];
+      static_for<0, N>([&](auto k) {
+        const C<T> e = w[decltype(k)::value * n2];
+        xr[decltype(k)::value] = e.re;
+        xi[decltype(k)::value] = e.im;
+      });
+      fft_reg<N, -1, T>(xr, xi);
+      const T *v = V + s * n3 + r;
+      static_for<0, N>([&](auto k) {
+        constexpr int kk = decltype(k)::value;
+        const T a = v[kk * n2];
+        tr[kk] += double(a * xr[kk]);
+        ti[kk] += double(a * xi[kk]);
+      });
+    }
+    C<double> *o = TA + b * n3 + r;
+    static_for<0, N>([&](auto k) {
+      o[decltype(k)::value * n2] = C<double>{tr[decltype(k)::value], ti[decltype(k)::value]};
+    });
+  }
+};
+
+// ----------------------------------------------------------------------------
 template <typename T, int N>
 struct Engine {
   using P = Passes<T, N>;
@@ -590,9 +753,9 @@ struct Engine {
   // product and back to the spectrum along axis 1, and the weighted slab
   // accumulation over q into the pair's half spectrum W; then the node sum and
   // the half-spectrum tail of the fused schedule.
-  static qcoll_status eval_vss(const Plan &p, const C<T> *H, const C<double> *H64, T *A, C<T> *Y, C<T> *TA,
+  static qcoll_status eval_vss(const Plan &p, const C<T> *H, const C<double> *H64, T *A, C<T> *Y, C<double> *TA,
                                C<T> *VP, C<double> *LH, const double *fb, double *Qb, long nb, long pc,
-                               hipStream_t st) {
+                               hipStream_t st, const double *isc, int K, long b0) {
     constexpr int H1 = N / 2 + 1;
     constexpr long nh = long(H1) * N * N;
     constexpr int SPB = slab_spb2<T, N>();
@@ -619,8 +782,8 @@ struct Engine {
     {
       TimedLaunch tl("sum nodes", st);
       if constexpr (std::is_same<T, float>::value) {
-        hipLaunchKernelGGL(k_sum_nodes, dim3(nblk(nb * (nh / 2), 256)), dim3(256), 0, st,
-                           reinterpret_cast<const float4 *>(Wp), reinterpret_cast<float4 *>(TA), nb, p.N_rho, nh / 2,
+        hipLaunchKernelGGL(k_sum_nodes_wide, dim3(nblk(nb * (nh / 2), 256)), dim3(256), 0, st,
+                           reinterpret_cast<const float4 *>(Wp), reinterpret_cast<double2 *>(TA), nb, p.N_rho, nh / 2,
                            n3 / 2);
       } else {
         hipLaunchKernelGGL(k_sum_nodes64, dim3(nblk(nb * nh, 256)), dim3(256), 0, st,
@@ -629,19 +792,66 @@ struct Engine {
       }
       QC_LAUNCH_CHECK("sum nodes");
     }
-    if ((s = slab<SrcCplxHalf<T, N>, DstCplxHalf<T, N>, +1>(SrcCplxHalf<T, N>{TA}, DstCplxHalf<T, N>{TA}, nb * H1, st,
-                                                             "gain inverse slab")))
+    if ((s = Passes<double, N>::template slab<SrcCplxHalf<double, N>, DstCplxHalf<double, N>, +1>(
+             SrcCplxHalf<double, N>{TA}, DstCplxHalf<double, N>{TA}, nb * H1, st, "gain inverse slab")))
       return s;
     if ((s = Passes<double, N>::template slab<SrcLossHalf<N>, DstCplxHalf<double, N>, +1>(
              SrcLossHalf<N>{H64, reinterpret_cast<const double *>(p.lam)}, DstCplxHalf<double, N>{LH}, nb * H1, st,
              "loss slab")))
       return s;
-    return pencil(OpAssembleHalf<T, N>{TA, LH, fb, Qb}, nb * N * N, st, "assemble");
+    return pencil(OpAssembleHalf<double, N>{TA, LH, fb, Qb, isc, K, b0}, nb * N * N, st, "assemble");
+  }
+
+  // literal Nyquist convention (two-pass, complex intermediates), see above
+  static qcoll_status eval_literal(const Plan &p, const C<T> *H, const C<double> *H64, T *Ar, T *Br, C<T> *W,
+                                   C<double> *TA, C<double> *LH, C<T> *Ya, C<T> *Yb, const double *fb, double *Qb,
+                                   long nb, long pc, hipStream_t st, const double *isc, int K, long b0) {
+    C<T> *A = reinterpret_cast<C<T> *>(Ar);
+    const long nbp = nb * p.N_rho;
+    const T scale = T(1.0 / double(n3));
+    const C<T> *ph = reinterpret_cast<const C<T> *>(p.phase);
+    qcoll_status s;
+    for (long bp0 = 0; bp0 < nbp; bp0 += pc) {
+      const long cnt = (nbp - bp0 < pc) ? (nbp - bp0) : pc;
+      SrcShiftPart<T, N, false> sa{H, ph, bp0, p.M, p.N_rho, scale};
+      SrcShiftPart<T, N, true> sb{H, ph, bp0, p.M, p.N_rho, scale};
+      if ((s = slab<SrcShiftPart<T, N, false>, DstCplx<T, N>, +1>(sa, DstCplx<T, N>{Ya}, cnt * p.M * N, st,
+                                                                   "gain slab")))
+        return s;
+      if ((s = slab<SrcShiftPart<T, N, true>, DstCplx<T, N>, +1>(sb, DstCplx<T, N>{Yb}, cnt * p.M * N, st,
+                                                                  "gain slab")))
+        return s;
+      OpGainAccLit<T, N> op{Ya, Yb, reinterpret_cast<const T *>(p.wq), A, bp0, p.M};
+      if ((s = pencil(op, cnt * N * N, st, "gain pencil"))) return s;
+    }
+    // rows of the low-rank stage: B_s = sum_p U_sp A_p (complex: re and im mixed alike)
+    const C<T> *Bsrc = A;
+    const int S = p.nv;
+    if (!p.mix_identity) {
+      TimedLaunch tl("mix", st);
+      launch_mix<T>(Ar, reinterpret_cast<const T *>(p.umix_d), Br, nb, S, p.N_rho, 2 * n3, st);
+      QC_LAUNCH_CHECK("mix");
+      Bsrc = reinterpret_cast<const C<T> *>(Br);
+    }
+    // the low-rank stage in FP64 (the workspace row W holds FP64 volumes)
+    C<double> *Wd = reinterpret_cast<C<double> *>(W);
+    if ((s = Passes<double, N>::template slab<SrcCplxWide<T, N, double>, DstCplx<double, N>, -1>(
+             SrcCplxWide<T, N, double>{Bsrc}, DstCplx<double, N>{Wd}, nb * S * N, st, "low-rank slab")))
+      return s;
+    if ((s = pencil(OpLowRankC<double, N>{Wd, p.v64(), TA, S}, nb * N * N, st, "low-rank pencil"))) return s;
+    if ((s = Passes<double, N>::template slab<SrcCplx<double, N>, DstCplx<double, N>, +1>(
+             SrcCplx<double, N>{TA}, DstCplx<double, N>{TA}, nb * N, st, "gain inverse slab")))
+      return s;
+    if ((s = Passes<double, N>::template slab<SrcLoss<N>, DstCplx<double, N>, +1>(
+             SrcLoss<N>{H64, reinterpret_cast<const double *>(p.lam)}, DstCplx<double, N>{LH}, nb * N, st,
+             "loss slab")))
+      return s;
+    return pencil(OpAssemble<double, N>{TA, LH, fb, Qb, isc, K, b0}, nb * N * N, st, "assemble");
   }
 
   // Q(f, f), or the bilinear Q(f, g) when g is non-null (two-pass schedule)
   static qcoll_status eval(const Plan &p, int64_t batch, const double *f, const double *g, double *Q, void *ws,
-                           const Layout &lay, hipStream_t st) {
+                           const Layout &lay, hipStream_t st, const double *isc, int K) {
     char *w = static_cast<char *>(ws);
     C<T> *Hg = reinterpret_cast<C<T> *>(w + lay.off_hg);
     C<double> *H64g = reinterpret_cast<C<double> *>(w + lay.off_h64g);
@@ -651,7 +861,7 @@ struct Engine {
     T *A = reinterpret_cast<T *>(w + lay.off_a);
     T *B = reinterpret_cast<T *>(w + lay.off_b);
     C<T> *W = reinterpret_cast<C<T> *>(w + lay.off_w);
-    C<T> *TA = reinterpret_cast<C<T> *>(w + lay.off_t);
+    C<double> *TA = reinterpret_cast<C<double> *>(w + lay.off_t);   // gain spectrum, FP64 in both precisions
     C<double> *LH = reinterpret_cast<C<double> *>(w + lay.off_l);
     C<T> *Y = reinterpret_cast<C<T> *>(w + lay.off_y);
     C<T> *VP = reinterpret_cast<C<T> *>(w + lay.off_vp);
@@ -667,8 +877,15 @@ struct Engine {
       } else {
         if ((s = Passes<double, N>::forward(fb, H64, nb, st))) return s;
       }
-      if (p.is_vss()) {
-        if ((s = eval_vss(p, H, H64, A, Y, TA, VP, LH, fb, Q + b0 * n3, nb, lay.pc, st))) return s;
+      if constexpr (N <= 48) {   // VSS kernels: N <= 48 (the plan refuses larger grids)
+        if (p.is_vss()) {
+          if ((s = eval_vss(p, H, H64, A, Y, TA, VP, LH, fb, Q + b0 * n3, nb, lay.pc, st, isc, K, b0))) return s;
+          continue;
+        }
+      }
+      if (p.literal) {
+        if ((s = eval_literal(p, H, H64, A, B, W, TA, LH, Y, Yg, fb, Q + b0 * n3, nb, lay.pc, st, isc, K, b0)))
+          return s;
         continue;
       }
       if (g) {
@@ -687,19 +904,20 @@ struct Engine {
           {
             // nh and n3 are even for every supported N, so the float4 view is exact
             TimedLaunch tl("sum nodes", st);
-            hipLaunchKernelGGL(k_sum_nodes, dim3(nblk(nb * (nh / 2), 256)), dim3(256), 0, st,
-                               reinterpret_cast<const float4 *>(Wp), reinterpret_cast<float4 *>(TA), nb, p.N_rho,
+            hipLaunchKernelGGL(k_sum_nodes_wide, dim3(nblk(nb * (nh / 2), 256)), dim3(256), 0, st,
+                               reinterpret_cast<const float4 *>(Wp), reinterpret_cast<double2 *>(TA), nb, p.N_rho,
                                nh / 2, n3 / 2);
             QC_LAUNCH_CHECK("sum nodes");
           }
-          if ((s = slab<SrcCplxHalf<T, N>, DstCplxHalf<T, N>, +1>(SrcCplxHalf<T, N>{TA}, DstCplxHalf<T, N>{TA},
-                                                                   nb * H1, st, "gain inverse slab")))
+          if ((s = Passes<double, N>::template slab<SrcCplxHalf<double, N>, DstCplxHalf<double, N>, +1>(
+                   SrcCplxHalf<double, N>{TA}, DstCplxHalf<double, N>{TA}, nb * H1, st, "gain inverse slab")))
             return s;
           if ((s = Passes<double, N>::template slab<SrcLossHalf<N>, DstCplxHalf<double, N>, +1>(
                    SrcLossHalf<N>{H64, reinterpret_cast<const double *>(p.lam)}, DstCplxHalf<double, N>{LH}, nb * H1,
                    st, "loss slab")))
             return s;
-          if ((s = pencil(OpAssembleHalf<T, N>{TA, LH, fb, Q + b0 * n3}, nb * N * N, st, "assemble"))) return s;
+          if ((s = pencil(OpAssembleHalf<double, N>{TA, LH, fb, Q + b0 * n3, isc, K, b0}, nb * N * N, st, "assemble")))
+            return s;
           continue;
         }
         if ((s = gain_terms(p, H, A, Y, nb, lay.pc, st))) return s;
@@ -713,19 +931,22 @@ struct Engine {
         QC_LAUNCH_CHECK("mix");
         Bsrc = B;
       }
-      if ((s = slab<SrcPair<T, N>, DstCplx<T, N>, -1>(SrcPair<T, N>{Bsrc, S, np}, DstCplx<T, N>{W}, nb * np * N, st,
-                                                        "low-rank slab")))
+      // the low-rank slab pass in FP64 in both precisions (W holds FP64 volumes)
+      C<double> *Wd = reinterpret_cast<C<double> *>(W);
+      if ((s = Passes<double, N>::template slab<SrcPair<T, N, double>, DstCplx<double, N>, -1>(
+               SrcPair<T, N, double>{Bsrc, S, np}, DstCplx<double, N>{Wd}, nb * np * N, st, "low-rank slab")))
         return s;
-      OpLowRank<T, N> lr{W, reinterpret_cast<const T *>(p.V), TA, np};
+      OpLowRank<T, N> lr{Wd, reinterpret_cast<const T *>(p.V), TA, np};
       if ((s = pencil(lr, nb * N * N, st, "low-rank pencil"))) return s;
-      if ((s = slab<SrcCplx<T, N>, DstCplx<T, N>, +1>(SrcCplx<T, N>{TA}, DstCplx<T, N>{TA}, nb * N, st,
-                                                        "gain inverse slab")))
+      if ((s = Passes<double, N>::template slab<SrcCplx<double, N>, DstCplx<double, N>, +1>(
+               SrcCplx<double, N>{TA}, DstCplx<double, N>{TA}, nb * N, st, "gain inverse slab")))
         return s;
       if ((s = Passes<double, N>::template slab<SrcLoss<N>, DstCplx<double, N>, +1>(
                SrcLoss<N>{g ? H64g : H64, reinterpret_cast<const double *>(p.lam)}, DstCplx<double, N>{LH}, nb * N,
                st, "loss slab")))
         return s;
-      if ((s = pencil(OpAssemble<T, N>{TA, LH, fb, Q + b0 * n3}, nb * N * N, st, "assemble"))) return s;
+      if ((s = pencil(OpAssemble<double, N>{TA, LH, fb, Q + b0 * n3, isc, K, b0}, nb * N * N, st, "assemble")))
+        return s;
     }
     return QCOLL_OK;
   }
@@ -737,7 +958,7 @@ struct Engine {
 // velocity of a point is rebuilt from its index.  The five sums are reduced
 // in a fixed order, so the result is deterministic.
 __global__ __launch_bounds__(1024) void k_conserve(double *Q, double *mom, const double *ginv, int N, double L,
-                                                   int *flag, double dc3) {
+                                                   int *flag, double dc3, const double *isc, int K) {
   const long n3 = long(N) * N * N;
   const long b = blockIdx.x;
   double2 *q = reinterpret_cast<double2 *>(Q + b * n3);
@@ -768,6 +989,7 @@ __global__ __launch_bounds__(1024) void k_conserve(double *Q, double *mom, const
   }
   double m[5], lam[5];
   for (int k = 0; k < 5; ++k) m[k] = red[k][0];
+  const double sc = isc ? isc[b % K] : 1.0;   // projection first, then the item's weight
   for (int a = 0; a < 5; ++a) {
     double acc = 0;
     for (int c = 0; c < 5; ++c) acc += ginv[a * 5 + c] * m[c];
@@ -789,6 +1011,8 @@ __global__ __launch_bounds__(1024) void k_conserve(double *Q, double *mom, const
     double2 v = q[h];
     v.x -= base + lam[3] * c3a + lam[4] * c3a * c3a;
     v.y -= base + lam[3] * c3b + lam[4] * c3b * c3b;
+    v.x *= sc;
+    v.y *= sc;
     q[h] = v;
   }
 }
@@ -858,10 +1082,10 @@ __global__ __launch_bounds__(256) void k_moments(const double *F, double *out, i
 
 // ----------------------------------------------------------------------------
 bool use_fused_gain(const Plan &p) {
-  return p.schedule != 1 && fused_gain_supported(p.N, p.precision);
+  return p.schedule != 1 && !p.literal && fused_gain_supported(p.N, p.precision);
 }
 
-Layout make_layout(const Plan &p, int64_t batch, int op) {
+Layout make_layout(const Plan &p, int64_t batch, int op, long chunk) {
   Layout l;
   const size_t es = (p.precision == QCOLL_FP32) ? sizeof(float) : sizeof(double);
   const long n3 = p.n3();
@@ -908,15 +1132,17 @@ Layout make_layout(const Plan &p, int64_t batch, int op) {
     l.total = o;
     return l;
   }
-  const long cmax = p.chunk > 0 ? p.chunk : 64;
+  const long cmax = chunk > 0 ? chunk : (p.chunk > 0 ? p.chunk : 64);
   l.bc = batch < cmax ? (batch > 0 ? batch : 1) : cmax;
   const bool bil = (op == 2);
   // two-pass hot loop: (item, node) pairs per launch such that the launch's
   // intermediate volume Y (M complex volumes per pair) stays near 192 MiB and
   // is mostly served from the 256 MiB Infinity Cache when the pencil pass
   // reads it back (FP64 at N = 32: 32 pairs)
+  const bool lit = p.literal && !bil;
   {
-    const size_t per_pair = size_t(p.M) * n3 * 2 * es;
+    // (the literal convention writes two volumes per term)
+    const size_t per_pair = size_t(p.M) * n3 * 2 * es * (lit ? 2 : 1);
     long pc = long((size_t(192) << 20) / per_pair);
     l.pc = pc < 8 ? 8 : (pc > 128 ? 128 : pc);
   }
@@ -928,17 +1154,21 @@ Layout make_layout(const Plan &p, int64_t batch, int op) {
   const bool vss = p.is_vss();
   // fused and VSS: W, the complex half spectra ((N/2 + 1) N^2 values) of every (item, node)
   const bool half = fused || vss;
-  const size_t per_node = half ? size_t(p.N / 2 + 1) * p.N * p.N * 2 : size_t(n3);
+  // literal: complex accumulators and one complex low-rank row per kept term
+  const size_t per_node = half ? size_t(p.N / 2 + 1) * p.N * p.N * 2 : size_t(n3) * (lit ? 2 : 1);
   l.off_a = o; o += al(size_t(l.bc) * p.N_rho * per_node * es);
-  l.off_b = o; o += (p.mix_identity || half) ? 0 : al(size_t(l.bc) * p.nv * n3 * es);
-  l.off_w = o; o += half ? 0 : al(size_t(l.bc) * p.npair() * n3 * 2 * es);
-  l.off_t = o; o += al(size_t(l.bc) * n3 * 2 * es);
+  l.off_b = o; o += (p.mix_identity || half) ? 0 : al(size_t(l.bc) * p.nv * n3 * es * (lit ? 2 : 1));
+  l.off_w = o; o += half ? 0 : al(size_t(l.bc) * (lit ? p.nv : p.npair()) * n3 * 2 * sizeof(double));
+  l.off_t = o; o += al(size_t(l.bc) * n3 * 2 * sizeof(double));   // gain spectrum, FP64
   l.off_l = o; o += al(size_t(l.bc) * n3 * 2 * sizeof(double));
   const bool q64 = use_gain_q64(p) && !bil;   // FP64 gain on chip: no per-term volumes
   l.off_y = o; o += (fused || q64) ? 0 : al(size_t(l.pc) * p.M * n3 * 2 * es);
   // two-pass VSS: the partial half spectra of the accumulation's parts 1.. of a launch
   l.off_vp = o;
   o += (vss && !fused && !bil) ? al(size_t(kVssParts - 1) * l.pc * (p.N / 2 + 1) * p.N * p.N * 2 * es) : 0;
+  if (lit) {
+    l.off_yg = o; o += al(size_t(l.pc) * p.M * n3 * 2 * es);   // the Im(beta) volumes
+  }
   if (bil) {
     l.off_hg = o; o += al(size_t(l.bc) * n3 * 2 * es);
     l.off_h64g = o; o += al(size_t(l.bc) * n3 * 2 * sizeof(double));
@@ -950,35 +1180,37 @@ Layout make_layout(const Plan &p, int64_t batch, int op) {
 
 template <typename T>
 static qcoll_status eval_dispatch(const Plan &p, int64_t batch, const double *f, const double *g, double *Q, void *ws,
-                                  const Layout &lay, hipStream_t st) {
+                                  const Layout &lay, hipStream_t st, const double *isc, int K) {
   switch (p.N) {
-    case 8: return Engine<T, 8>::eval(p, batch, f, g, Q, ws, lay, st);
-    case 12: return Engine<T, 12>::eval(p, batch, f, g, Q, ws, lay, st);
-    case 16: return Engine<T, 16>::eval(p, batch, f, g, Q, ws, lay, st);
-    case 24: return Engine<T, 24>::eval(p, batch, f, g, Q, ws, lay, st);
-    case 32: return Engine<T, 32>::eval(p, batch, f, g, Q, ws, lay, st);
-    case 48: return Engine<T, 48>::eval(p, batch, f, g, Q, ws, lay, st);
+    case 8: return Engine<T, 8>::eval(p, batch, f, g, Q, ws, lay, st, isc, K);
+    case 12: return Engine<T, 12>::eval(p, batch, f, g, Q, ws, lay, st, isc, K);
+    case 16: return Engine<T, 16>::eval(p, batch, f, g, Q, ws, lay, st, isc, K);
+    case 24: return Engine<T, 24>::eval(p, batch, f, g, Q, ws, lay, st, isc, K);
+    case 32: return Engine<T, 32>::eval(p, batch, f, g, Q, ws, lay, st, isc, K);
+    case 48: return Engine<T, 48>::eval(p, batch, f, g, Q, ws, lay, st, isc, K);
+    case 64: return Engine<T, 64>::eval(p, batch, f, g, Q, ws, lay, st, isc, K);
     default: set_error("unsupported N"); return QCOLL_ENOTSUP;
   }
 }
 
 qcoll_status launch_eval(const Plan &p, int64_t batch, const double *f, double *Q, void *ws,
-                         const Layout &lay, hipStream_t st) {
-  if (p.precision == QCOLL_FP32) return eval_dispatch<float>(p, batch, f, nullptr, Q, ws, lay, st);
-  return eval_dispatch<double>(p, batch, f, nullptr, Q, ws, lay, st);
+                         const Layout &lay, hipStream_t st, const double *isc, int K) {
+  if (p.precision == QCOLL_FP32) return eval_dispatch<float>(p, batch, f, nullptr, Q, ws, lay, st, isc, K);
+  return eval_dispatch<double>(p, batch, f, nullptr, Q, ws, lay, st, isc, K);
 }
 
 qcoll_status launch_eval2(const Plan &p, int64_t batch, const double *f, const double *g, double *Q, void *ws,
                           const Layout &lay, hipStream_t st) {
-  if (p.precision == QCOLL_FP32) return eval_dispatch<float>(p, batch, f, g, Q, ws, lay, st);
-  return eval_dispatch<double>(p, batch, f, g, Q, ws, lay, st);
+  if (p.precision == QCOLL_FP32) return eval_dispatch<float>(p, batch, f, g, Q, ws, lay, st, nullptr, 0);
+  return eval_dispatch<double>(p, batch, f, g, Q, ws, lay, st, nullptr, 0);
 }
 
-qcoll_status launch_conserve(const Plan &p, int64_t batch, double *Q, double *mom, hipStream_t st) {
+qcoll_status launch_conserve(const Plan &p, int64_t batch, double *Q, double *mom, hipStream_t st, const double *isc,
+                             int K) {
   const double dc = 2.0 * p.L / p.N;
   TimedLaunch tl("conserve", st);
   hipLaunchKernelGGL(k_conserve, dim3(unsigned(batch)), dim3(1024), 0, st, Q, mom, p.ginv, p.N, p.L, p.flag,
-                     dc * dc * dc);
+                     dc * dc * dc, isc, K);
   QC_LAUNCH_CHECK("conserve");
   return QCOLL_OK;
 }

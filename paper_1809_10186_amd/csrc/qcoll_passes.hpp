@@ -48,10 +48,12 @@ constexpr int slab_spb2() {
 }
 
 // k_slab moves one component at a time through LDS (more barriers, half the
-// tile) where that turns blocks with idle lanes into whole waves (N = 48 in FP32)
+// tile) where that turns blocks with idle lanes into whole waves (N = 48 in
+// FP32), or where both components of one slab exceed 64 KiB (N = 64 in FP64)
 template <typename T, int N>
 constexpr bool slab_split() {
-  return lane_use_pct(N, slab_spb2<T, N>()) < 80 && lane_use_pct(N, spb_for(N, N * (N + 1) * int(sizeof(T)))) == 100;
+  return 2 * N * (N + 1) * int(sizeof(T)) > 65536 ||
+         (lane_use_pct(N, slab_spb2<T, N>()) < 80 && lane_use_pct(N, spb_for(N, N * (N + 1) * int(sizeof(T)))) == 100);
 }
 
 template <typename T, int N>

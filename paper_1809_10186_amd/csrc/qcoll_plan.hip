@@ -128,7 +128,7 @@ qcoll_status upload(const std::vector<double> &h, void **dptr) {
 }  // namespace
 
 bool supported_N(int N) {
-  return N == 8 || N == 12 || N == 16 || N == 24 || N == 32 || N == 48;
+  return N == 8 || N == 12 || N == 16 || N == 24 || N == 32 || N == 48 || N == 64;
 }
 
 // Kernel tables for the current omega/prefactor (alpha_p rows, Lambda, Lambda_p).
@@ -217,6 +217,7 @@ static qcoll_status upload_kernel_tables(Plan &p) {
     return p.precision == QCOLL_FP32 ? upload<float>(h, d) : upload<double>(h, d);
   };
   if ((st = up(Vs, &p.V)) != QCOLL_OK) return st;
+  if (p.precision == QCOLL_FP32 && (st = upload<double>(Vs, reinterpret_cast<void **>(&p.V64))) != QCOLL_OK) return st;
   if ((st = upload<double>(lams, &p.lam)) != QCOLL_OK) return st;
   if ((st = up(U, &p.umix_d)) != QCOLL_OK) return st;
   p.umix = U;
@@ -293,6 +294,7 @@ static qcoll_status upload_truncated(Plan &p, int svd_rank, double svd_tol) {
     return p.precision == QCOLL_FP32 ? upload<float>(h, d) : upload<double>(h, d);
   };
   if ((st = up(Vs, &p.V)) != QCOLL_OK) return st;
+  if (p.precision == QCOLL_FP32 && (st = upload<double>(Vs, reinterpret_cast<void **>(&p.V64))) != QCOLL_OK) return st;
   if ((st = upload<double>(lams, &p.lam)) != QCOLL_OK) return st;
   if ((st = up(U, &p.umix_d)) != QCOLL_OK) return st;
   p.umix = U;
@@ -466,6 +468,7 @@ static double kernel_constant(double omega, double alpha) {
 
 static void free_kernel_tables(Plan &p) {
   (void)hipFree(p.V);
+  (void)hipFree(p.V64);
   (void)hipFree(p.lam);
   (void)hipFree(p.umix_d);
   (void)hipFree(p.lam_p);
@@ -474,6 +477,7 @@ static void free_kernel_tables(Plan &p) {
   (void)hipFree(p.alpha_pq);
   p.alpha_eff = p.alpha_pq = nullptr;
   p.V = p.lam = p.umix_d = nullptr;
+  p.V64 = nullptr;
   p.lam_p = p.dlog = nullptr;
 }
 
@@ -484,6 +488,7 @@ qcoll_status plan_build(Plan &p, const qcoll_params &prm) {
   p.omega = prm.omega;
   p.precision = prm.precision;
   p.vss = prm.alpha;
+  p.literal = prm.nyquist == QCOLL_NYQ_LITERAL;
   p.b_follows_omega = !(prm.prefactor > 0.0);
   p.b = p.b_follows_omega ? kernel_constant(p.omega, p.vss) : prm.prefactor;
   p.R = 4.0 * p.L / (3.0 + std::sqrt(2.0));
@@ -509,7 +514,7 @@ qcoll_status plan_build(Plan &p, const qcoll_params &prm) {
         for (int n = 0; n < N; ++n) {
           const double th = kPiD * kappa(n, N) * s / p.L;
           double re = std::cos(th), im = std::sin(th);
-          if (n == N / 2) im = 0.0;  // cosine mode of the real interpolant
+          if (n == N / 2 && !p.literal) im = 0.0;  // cosine mode of the real interpolant
           const size_t o = ((((size_t(r) * p.M + q) * 3 + d) * N) + n) * 2;
           ph[o] = re;
           ph[o + 1] = im;
@@ -587,6 +592,7 @@ qcoll_status plan_set_omega(Plan &p, double omega) {
   Plan t = p;
   t.alpha_eff = t.alpha_pq = nullptr;
   t.V = t.lam = t.umix_d = nullptr;
+  t.V64 = nullptr;
   t.lam_p = t.dlog = nullptr;
   t.omega = omega;
   if (t.b_follows_omega) t.b = kernel_constant(t.omega, t.vss);

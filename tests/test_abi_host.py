@@ -45,14 +45,17 @@ def test_valid_params_pass():
     assert code == 0
     assert qc.params_check(**ok_kw(sphere=None))[0] == 0
     assert qc.params_check(**ok_kw(svd_rank=0, svd_tol=1e-8))[0] == 0
-    for N in (8, 12, 24, 32, 48):
+    for N in (8, 12, 24, 32, 48, 64):
         assert qc.params_check(**ok_kw(N=N))[0] == 0
     for a in (1.2, 1.5, 2.0):    # VSS kernels with the full table
         assert qc.params_check(**ok_kw(alpha=a))[0] == 0
+    assert qc.params_check(**ok_kw(nyquist="literal"))[0] == 0
+    assert qc.params_check(**ok_kw(nyquist="literal", svd_rank=0, svd_tol=1e-6))[0] == 0
 
 
 @pytest.mark.parametrize("over,code,frag", [
-    (dict(N=0), 1, "N"), (dict(N=15), 1, "even"), (dict(N=20), 2, "one of"), (dict(N=64), 2, "one of"),
+    (dict(N=0), 1, "N"), (dict(N=15), 1, "even"), (dict(N=20), 2, "one of"), (dict(N=96), 2, "one of"),
+    (dict(N=64, alpha=1.5), 2, "VSS"),
     (dict(L=0.0), 1, "L"), (dict(L=float("nan")), 1, "L"), (dict(L=-1.0), 1, "L"),
     (dict(N_rho=0), 1, "N_rho"), (dict(N_rho=65), 2, "N_rho"),
     (dict(omega=0.4), 1, "omega"), (dict(omega=1.2), 1, "omega"),
@@ -61,6 +64,7 @@ def test_valid_params_pass():
     (dict(precision=7), 1, "precision"),
     (dict(svd_rank=0, svd_tol=0.0), 1, "svd_tol"), (dict(svd_rank=99), 1, "svd_rank"),
     (dict(prefactor=float("inf")), 1, "prefactor"),
+    (dict(nyquist=2), 1, "nyquist"), (dict(nyquist="literal", alpha=1.5), 2, "literal"),
 ])
 def test_invalid_params_rejected(over, code, frag):
     c, msg = qc.params_check(**ok_kw(**over))
@@ -88,3 +92,20 @@ def test_builtin_rule_is_the_icosahedral_one():
     import ctypes
     assert qc.lib().qcoll_params_check(ctypes.byref(p)) == 1
     assert math.isclose(sum(W.sphere_rule(6)[1]), 2 * math.pi)
+
+
+def test_qcoll_log_reports_argument_errors():
+    """QCOLL_LOG=1 turns on the library's stderr diagnostics (read once per
+    process); argument errors are reported there as well as by qcoll_last_error."""
+    import subprocess
+    import sys
+    code = ("import paper_1809_10186_amd as qc, workloads as W; "
+            "print(qc.params_check(N=15, L=6.0, N_rho=8, sphere=W.sphere_rule(12), omega=0.81)[0])")
+    env = dict(os.environ, QCOLL_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip() == "1"
+    assert "[qcoll] error: N must be a positive even integer" in r.stderr
+    env["QCOLL_LOG"] = "0"
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True, timeout=120)
+    assert "[qcoll]" not in r.stderr

@@ -66,3 +66,38 @@ def test_dg_fp32_path():
     C = plan.dg_collide(gpu(F), gpu(T), gpu(Wm)).cpu().numpy()
     # each term carries the FP32 bound of Q; the combination is a small sum
     assert np.abs(C - ref).max() <= 5e-5 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("precision", [qc.QCOLL_FP64, qc.QCOLL_FP32])
+@pytest.mark.parametrize("conserve", [False, True])
+def test_dg_collocated_form_matches_oracle_and_general_form(precision, conserve):
+    """Collocated form (T = I, W = diag(J w_m), no contraction, the weights
+    folded into the last store): against the oracle's w_m Q(F_m) (projected
+    first when conserve) and against the general entry point with those T, W.
+    Elements x nodes = 7 x 3 items at 16^3 (the FP32 plan runs the fused
+    schedule), with an item count that is not a multiple of the chunk."""
+    N, L, Nr = 16, 6.0, 8
+    nodes, w = dg.gauss_nodes(2)
+    K, E, J = 3, 7, 0.37
+    wj = J * w
+    F = np.stack([W.maxwellian_mixture(K, N, L, 1000 + e) for e in range(E)])
+    sph = W.sphere_rule(12)
+    Pp = spectral.Params(N, L, Nr, sph[0], sph[1], 0.81)
+    Q = spectral.collide_batch(F.reshape(-1, N, N, N), Pp).reshape(E, K, N, N, N)
+    if conserve:
+        Q = oc.project(Q.reshape(-1, N, N, N), N, L)[0].reshape(Q.shape)
+    ref = wj[None, :, None, None, None] * Q
+    plan = qc.Plan(N, L, Nr, sphere=sph, omega=0.81, precision=precision)
+    plan.set_chunk(8)
+    Fg = gpu(F)
+    C = plan.dg_collide_collocated(Fg, wj, conserve=conserve)
+    Cg = plan.dg_collide(Fg, gpu(np.eye(K)), gpu(np.diag(wj)), conserve=conserve)
+    tol = 1e-12 if precision == qc.QCOLL_FP64 else 2e-5
+    e_ref = float(np.abs(C.cpu().numpy() - ref).max() / np.abs(ref).max())
+    e_gen = float((C - Cg).abs().max() / Cg.abs().max())
+    print(f"collocated prec={precision} conserve={conserve}: vs oracle {e_ref:.3e}, vs general {e_gen:.3e}",
+          flush=True)
+    assert e_ref <= tol
+    assert e_gen <= 1e-14
+    if conserve:
+        assert np.all(oc.conservation_residual(C.cpu().numpy().reshape(-1, N, N, N), N, L) <= 1e-12)

@@ -75,9 +75,9 @@ def test_uneven_three_grid_group_forward_and_vjp():
         fs.append(f)
         fgs.append(gpu(f))
     print("ranks", [p.info()["rank"] for p in plans], flush=True)
-    for p, fg in zip(plans, fgs):
-        print(f"autotune N={p.N}: {p.autotune(fg)}", flush=True)
     grp = qc.Group(plans, [g["items"] for g in W.UNEVEN])
+    grp.autotune(fgs)
+    print("autotuned", [(p.N, p.info()["rank"]) for p in plans], flush=True)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         Qg = grp.eval(fgs, conserve=True, use_graph=True, stream=stream)
