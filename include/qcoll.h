@@ -185,6 +185,19 @@ size_t qcoll_workspace_bytes(qcoll_plan plan, int64_t batch, int32_t op);
 qcoll_status qcoll_eval(qcoll_plan plan, int64_t batch, const double *f, double *Q,
                         void *ws, size_t ws_bytes, void *stream);
 
+/* qcoll_eval for callers that cannot allocate device memory or pass a
+ * workspace: code under hipGraph stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same result as qcoll_eval (same kernels;
+ * every item's result is independent of the chunking).  The scratch is one
+ * static device array of 256 MiB, one copy per GPU the library runs on, held
+ * until the process ends; the batch runs in chunks whose workspace fits it
+ * (at most the plan's chunk).  Calls no allocator.  EWORKSPACE if a single
+ * item of this plan needs more scratch than the array holds.  Every call on a
+ * GPU uses that GPU's one array: calls that overlap on one GPU (different
+ * streams or threads without ordering between them) race and give undefined
+ * results; order them on one stream. */
+qcoll_status qcoll_eval_noalloc(qcoll_plan plan, int64_t batch, const double *f, double *Q, void *stream);
+
 /* Bilinear collision operator Q(f, g) (Appendix: the operator form
  * Q(f,g) = int int B_sym [f(c') g(c'_*) - f(c) g(c_*)] evaluated with the same
  * quadrature form of the kernel modes): per (rho_p, sigma_q) the gain takes

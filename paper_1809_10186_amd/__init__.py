@@ -77,6 +77,7 @@ def lib():
             "qcoll_plan_set_schedule": ([vp, i32], i32),
             "qcoll_workspace_bytes": ([vp, i64, i32], ctypes.c_size_t),
             "qcoll_eval": ([vp, i64, dp, dp, vp, ctypes.c_size_t, vp], i32),
+            "qcoll_eval_noalloc": ([vp, i64, dp, dp, vp], i32),
             "qcoll_conserve": ([vp, i64, dp, dp, vp], i32),
             "qcoll_moments": ([vp, i64, dp, dp, vp], i32),
             "qcoll_vjp": ([vp, i64, dp, dp, dp, dp, i32, vp, ctypes.c_size_t, vp], i32),
@@ -297,6 +298,14 @@ class Plan:
             self._check_out(out, "out", f.shape)
         ws = self.workspace(batch, 0, stream)
         _check(lib().qcoll_eval(self._h, batch, _ptr(f), _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+        return out
+
+    def eval_noalloc(self, f, out, stream=None):
+        """qcoll_eval without a workspace and without any allocation (scratch in a
+        fixed device array of the library; calls on one GPU must not overlap)."""
+        batch = self._check_f(f, "f")
+        self._check_out(out, "out", f.shape)
+        _check(lib().qcoll_eval_noalloc(self._h, batch, _ptr(f), _ptr(out), _stream(stream)))
         return out
 
     def eval_bilinear(self, f, g, out=None, stream=None):

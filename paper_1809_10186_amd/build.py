@@ -58,7 +58,7 @@ def build(jobs=None):
 # built with a sanitizer); the kernel-heavy sources reuse the objects of
 # build().  The driver is linked by clang++, which brings the sanitizer runtimes.
 HOST_CHECK_SOURCES = ("qcoll_api.hip", "qcoll_plan.hip", "qcoll_group.hip", "qcoll_dg1d.hip", "qcoll_timing.hip",
-                      "qcoll_dg.hip")
+                      "qcoll_noalloc.hip", "qcoll_dg.hip")
 SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
              "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
 HOST_CHECK_DIR = os.path.join(ROOT, "tests", "host_check")

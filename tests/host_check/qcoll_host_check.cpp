@@ -144,6 +144,7 @@ static void check_plan(const qcoll_params &prm) {
     EXPECT(qcoll_eval(plan, batch, f, Q, ws, wsb, nullptr) == QCOLL_OK);
     EXPECT(qcoll_eval(plan, batch, f, Q, ws, wsb - 1, nullptr) == QCOLL_EWORKSPACE);
     EXPECT(qcoll_eval(plan, batch, f, f, ws, wsb, nullptr) == QCOLL_EINVAL);
+    EXPECT(qcoll_eval_noalloc(plan, batch, f, Q, nullptr) == QCOLL_OK);
     EXPECT(qcoll_conserve(plan, batch, Q, nullptr, nullptr) == QCOLL_OK);
     EXPECT(qcoll_poll(plan) == QCOLL_OK);
   } else {
