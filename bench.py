@@ -82,7 +82,7 @@ def model_flops_per_term(N):
     return model_flops_fft(N) + 23.0 * N ** 3
 
 
-def algorithmic_bytes(role, fp32, B, N, Nr, M, npair, nv):
+def algorithmic_bytes(role, fp32, B, N, Nr, M, npair, nv, half=None):
     """Bytes per step that a pass of the pipeline must move through HBM (item
     data only; the shared plan tables are read from cache): what each kernel
     role reads and writes once, by the layout of the workspace.  None for roles
@@ -90,33 +90,41 @@ def algorithmic_bytes(role, fp32, B, N, Nr, M, npair, nv):
     es = 4 if fp32 else 8           # working precision of the gain
     c = 2 * es                      # complex in the working precision
     n3, nh = N ** 3, (N // 2 + 1) * N * N
-    half = fp32                     # the fused schedule keeps half spectra
+    if half is None:
+        half = fp32                 # the fused schedule keeps half spectra
+    c64 = 16                        # complex FP64 (spectra, low-rank stage, gain inverse, assembly)
     m = {
         "forward slab": B * n3 * (8 + 16),
         "forward pencil": B * n3 * ((16 + 16 + 8) if fp32 else (16 + 16)),
-        "gain slab": B * Nr * M * n3 * (c + c),
+        # the item spectrum once (each of its Nr*M terms re-reads it from L2),
+        # every term's volume written once
+        "gain slab": B * n3 * c + B * Nr * M * n3 * c,
         "gain pencil": B * Nr * n3 * (M * c + es),
         "mix": B * n3 * (Nr + nv) * es,
-        "low-rank slab": B * npair * n3 * (2 * es + c),
-        "low-rank pencil": B * n3 * (npair * c + c),
-        "gain inverse slab": B * (nh if half else n3) * (c + c),
+        # two-pass low-rank stage in FP64 for both precisions: A_p pairs in,
+        # complex FP64 volumes out; then the pencil sum over the pairs
+        "low-rank slab": B * npair * n3 * (2 * es + c64),
+        "low-rank pencil": B * n3 * (npair * c64 + c64),
+        "gain inverse slab": B * (nh if half else n3) * (c64 + c64),
         "loss slab": B * (nh if half else n3) * (16 + 16),
-        "assemble": B * ((nh * (c + 16) + n3 * 16) if half else n3 * (c + 16 + 16)),
-        "sum nodes": B * nh * 8 * (Nr + 1),
+        # gain and loss spectra in (complex FP64), f in and Q out (FP64)
+        "assemble": B * ((nh * (c64 + 16) + n3 * 16) if half else n3 * (c64 + 16 + 16)),
+        # Nr FP32 half spectra in, one FP64 half spectrum out
+        "sum nodes": B * nh * (8 * Nr + 16),
         "conserve": B * n3 * (8 + 8),
         "gain fused": B * n3 * 8 + B * Nr * nh * 8,
     }
     return m.get(role)
 
 
-def hbm_passes(kt, steps, fp32, B, N, Nr, M, npair, nv):
+def hbm_passes(kt, steps, fp32, B, N, Nr, M, npair, nv, half=None):
     """Per kernel role: time per step, algorithmic bytes per step and the rate
     against the HBM peak (the on-chip gain kernel is ALU bound and listed
     with its bytes only)."""
     out = {}
     tot_b = tot_ms = 0.0
     for role, (ms, n) in sorted(kt.items(), key=lambda kv: -kv[1][0]):
-        b = algorithmic_bytes(role, fp32, B, N, Nr, M, npair, nv)
+        b = algorithmic_bytes(role, fp32, B, N, Nr, M, npair, nv, half)
         ms_step = ms / steps
         ent = {"ms_per_step": round(ms_step, 4), "launches_per_step": n / steps}
         if b is not None:
@@ -405,19 +413,25 @@ def uneven48(qc, torch, W, steps, warmup):
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
-        qc.timing_reset()
-        qc.timing_select(None)
-        qc.timing_enable(True)
+        # wall time without per-launch events, then the per-role breakdown in
+        # a second pass with them (several hundred launches per step here)
         t0 = time.perf_counter()
         for _ in range(steps):
             fn()
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps * 1e3
+        qc.timing_reset()
+        qc.timing_select(None)
+        qc.timing_enable(True)
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
         qc.timing_enable(False)
         kt = qc.timing_read()
         ent = {"ms": round(dt, 3)}
         if name == "eval_conserve":
-            passes, summ = hbm_passes(kt, steps, True, B, N, Nr, M, (inf["rank"] + 1) // 2, inf["rank"])
+            passes, summ = hbm_passes(kt, steps, True, B, N, Nr, M, (inf["rank"] + 1) // 2, inf["rank"],
+                                      half=False)
             ent.update({"hbm_passes": passes, "hbm_passes_total": summ})
         else:
             ent["kernel_ms"] = {k: round(v[0] / steps, 4) for k, v in kt.items()}

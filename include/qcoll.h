@@ -81,8 +81,7 @@ typedef enum { QCOLL_FP64 = 0, QCOLL_FP32 = 1 } qcoll_precision;
  *              (Appendix, F with the kernel symmetrised in cos chi): every
  *              (rho_p, sigma_q) term is then transformed forward and weighted
  *              on its own, about twice the work of alpha = 1.  VSS plans need
- *              svd_rank < 0; qcoll_vjp, qcoll_eval_bilinear and
- *              qcoll_dg_collide_svd return ENOTSUP for them.
+ *              svd_rank < 0 and N <= 48.
  *   prefactor  kernel constant b; a value <= 0 or NaN selects the
  *              non-dimensional constant alpha / (2^{2-omega+alpha}
  *              Gamma(2.5-omega) pi) (Section 2.1; 1/(2^{3-omega} Gamma(2.5-omega)
@@ -101,7 +100,7 @@ typedef enum { QCOLL_FP64 = 0, QCOLL_FP32 = 1 } qcoll_precision;
  *              shifted copies t1, t2 and the gain are complex and Q is the real
  *              part.  LITERAL plans run the two-pass schedule with two inverse
  *              transforms per term; qcoll_vjp, qcoll_eval_bilinear and
- *              qcoll_dg_collide_svd return ENOTSUP for them, as do VSS kernels.
+ *              qcoll_dg_collide_svd return ENOTSUP for them.
  */
 typedef enum { QCOLL_NYQ_SYMMETRIC = 0, QCOLL_NYQ_LITERAL = 1 } qcoll_nyquist;
 
@@ -201,9 +200,11 @@ qcoll_status qcoll_eval_noalloc(qcoll_plan plan, int64_t batch, const double *f,
 /* Bilinear collision operator Q(f, g) (Appendix: the operator form
  * Q(f,g) = int int B_sym [f(c') g(c'_*) - f(c) g(c_*)] evaluated with the same
  * quadrature form of the kernel modes): per (rho_p, sigma_q) the gain takes
- * (t1_f t2_g + t2_f t1_g) / 2, the loss is f * Lam~ g.  Q(f, f) equals
- * qcoll_eval.  Two inverse transforms per term (two-pass schedule in both
- * precisions).  f, g, Q: [batch][N^3]; workspace: qcoll_workspace_bytes(op 2). */
+ * (t1_f t2_g + t2_f t1_g) / 2 (for VSS kernels each term's product is weighted
+ * by its own alpha_pq after its transform), the loss is f * Lam~ g.  Q(f, f)
+ * equals qcoll_eval.  Two inverse transforms per term (two-pass schedule in both
+ * precisions).  f, g, Q: [batch][N^3]; workspace: qcoll_workspace_bytes(op 2).
+ * ENOTSUP for literal-Nyquist plans. */
 qcoll_status qcoll_eval_bilinear(qcoll_plan plan, int64_t batch, const double *f, const double *g,
                                  double *Q, void *ws, size_t ws_bytes, void *stream);
 
@@ -227,6 +228,8 @@ qcoll_status qcoll_moments(qcoll_plan plan, int64_t batch, const double *f, doub
  *   df = J_f^T g  ([batch][N^3], may be NULL),
  *   domega[b] = g_b . dQ(f_b)/d omega ([batch], may be NULL; needs an
  *   untruncated plan, else ENOTSUP).
+ * VHS and VSS kernels (VSS: the two-pass adjoint, one inverse transform of
+ * alpha_pq g^ per sphere point); N <= 48, symmetric Nyquist convention.
  * through_conserve != 0 differentiates the projected operator (g is first
  * projected; the projection is symmetric).  Not part of the paper's method. */
 qcoll_status qcoll_vjp(qcoll_plan plan, int64_t batch, const double *f, const double *g,

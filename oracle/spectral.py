@@ -148,11 +148,24 @@ def collide_fg(f, g, P):
     """Bilinear Q(f, g) of the Appendix (the operator the paper evaluates for
     the weak form): gain sum_{l+m=k} G(l,m) f^_l g^_m with the quadrature form
     of G, i.e. per (p, q) the product a_f a_g + b_f b_g of the cos- and
-    sin-weighted inverse transforms of f and g; loss f * ifft3(Lambda * fft3 g)."""
+    sin-weighted inverse transforms of f and g; loss f * ifft3(Lambda * fft3 g).
+    VSS kernels weight every (p, q) product by its own alpha_pq after its
+    transform, as in gain_vss."""
     f = np.asarray(f, dtype=float)
     g = np.asarray(g, dtype=float)
     Xf = dft.fft3(f)
     Xg = dft.fft3(g)
+    if P.vss:
+        Qh = np.zeros(f.shape, dtype=complex)
+        for p, rho in enumerate(P.kt.rho):
+            for q in range(P.M):
+                bt = beta(P.N, P.L, 0.5 * rho * P.sphere_pts[q], P.nyquist)
+                af = dft.ifft3(bt.real * Xf)
+                bf = dft.ifft3(bt.imag * Xf)
+                ag = dft.ifft3(bt.real * Xg)
+                bg = dft.ifft3(bt.imag * Xg)
+                Qh += P.alpha_pq[p, q] * dft.fft3(af * ag + bf * bg)
+        return (dft.ifft3(Qh) - f * dft.ifft3(P.lam * Xg)).real
     A = np.zeros((P.N_rho,) + f.shape, dtype=complex)
     for p, rho in enumerate(P.kt.rho):
         for q in range(P.M):

@@ -230,7 +230,6 @@ qcoll_status qcoll_eval_bilinear(qcoll_plan plan, int64_t batch, const double *f
   if (batch < 0) return fail(QCOLL_EINVAL, "batch must be >= 0");
   if (batch == 0) return QCOLL_OK;
   if (!f || !g || !Q) return fail(QCOLL_EINVAL, "f, g and Q must be non-NULL");
-  if (plan->p.is_vss()) return fail(QCOLL_ENOTSUP, "the bilinear Q needs a VHS plan (alpha = 1)");
   if (plan->p.literal) return fail(QCOLL_ENOTSUP, "the bilinear Q needs the symmetric Nyquist convention");
   const long n3 = plan->p.n3();
   auto overlap = [&](const void *a) {
@@ -273,7 +272,6 @@ qcoll_status qcoll_vjp(qcoll_plan plan, int64_t batch, const double *f, const do
   if (batch < 0) return fail(QCOLL_EINVAL, "batch must be >= 0");
   if (batch == 0) return QCOLL_OK;
   if (!f || !g) return fail(QCOLL_EINVAL, "f and g must be non-NULL");
-  if (plan->p.is_vss()) return fail(QCOLL_ENOTSUP, "the VJP needs a VHS plan (alpha = 1)");
   if (plan->p.literal) return fail(QCOLL_ENOTSUP, "the VJP needs the symmetric Nyquist convention");
   if (plan->p.N > 48) return fail(QCOLL_ENOTSUP, "the VJP supports N <= 48");
   if (!df && !domega) return QCOLL_OK;
@@ -397,7 +395,6 @@ qcoll_status qcoll_dg_collide_svd(qcoll_plan plan, int64_t n_elem, int32_t K, in
   if (K < 1 || K > 64 || R < 1 || R > 4096) return fail(QCOLL_EINVAL, "need 1 <= K <= 64 and 1 <= R <= 4096");
   if (n_elem == 0) return QCOLL_OK;
   if (!T1 || !T2 || !W || !F || !C) return fail(QCOLL_EINVAL, "T1, T2, W, F and C must be non-NULL");
-  if (plan->p.is_vss()) return fail(QCOLL_ENOTSUP, "the bilinear Q needs a VHS plan (alpha = 1)");
   if (plan->p.literal) return fail(QCOLL_ENOTSUP, "the bilinear Q needs the symmetric Nyquist convention");
   const size_t n3 = size_t(plan->p.n3());
   const size_t terms = size_t(n_elem) * R;

@@ -242,9 +242,8 @@ qcoll_status qcoll_group_vjp(qcoll_group g, const double *const *f, const double
                              void *stream, int32_t use_graph) {
   if (g)
     for (size_t i = 0; i < g->plans.size(); ++i)
-      if (g->plans[i]->p.is_vss() || g->plans[i]->p.literal || g->plans[i]->p.N > 48)
-        return gfail(QCOLL_ENOTSUP,
-                     "the VJP needs VHS plans (alpha = 1) with the symmetric Nyquist convention and N <= 48");
+      if (g->plans[i]->p.literal || g->plans[i]->p.N > 48)
+        return gfail(QCOLL_ENOTSUP, "the VJP needs plans with the symmetric Nyquist convention and N <= 48");
   if (g && domega)
     for (size_t i = 0; i < g->plans.size(); ++i)
       if (domega[i] && g->plans[i]->p.truncated)

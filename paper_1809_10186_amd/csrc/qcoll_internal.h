@@ -71,6 +71,7 @@ struct Layout {
   size_t off_h = 0, off_h64 = 0, off_a = 0, off_b = 0, off_w = 0, off_t = 0, off_l = 0, off_y = 0;
   size_t off_g = 0, off_z = 0, off_hp = 0, off_d = 0, off_pm = 0, off_dp = 0;  // vjp extras
   size_t off_pd = 0;                                    // two-pass vjp: per-pencil omega-gradient parts
+  size_t off_yh = 0;                                    // two-pass VSS vjp: paired h_pq volumes
   size_t off_vp = 0;                                    // two-pass VSS eval: partial half spectra
   size_t off_hg = 0, off_h64g = 0, off_yg = 0;          // bilinear extras
   size_t total = 0;

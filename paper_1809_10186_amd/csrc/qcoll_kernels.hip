@@ -213,13 +213,10 @@ struct SrcPair {
 // low-rank stage, pencil pass: forward along the first axis for each pair s,
 // accumulating T += (V_2s - i V_2s+1) Z^_s (V already carries 1/N^3).
 // With Z = B_2s + i B_2s+1 and V real and even, Re ifft(T) = sum_s C_s B_s.
-// The slab pass before it runs in FP64 in both precisions and leaves FP64
-// volumes W; this pass transforms in the working precision T and stores the
-// gain spectrum in FP64.  (Gain and loss cancel by up to two orders of
-// magnitude in Q: an FP32 gain spectrum and inverse transform cost about 2e-5
-// of ||Q||, an FP32 two-axis forward transform of the accumulators about half
-// of that; the remaining FP32 axis and sums cost a few 1e-6 and keep this
-// pass's registers within two waves per SIMD at N = 48.)
+// The low-rank stage (this pass and the slab pass before it) runs in FP64 in
+// both precisions: gain and loss cancel by up to two orders of magnitude in Q,
+// and an FP32 gain spectrum and inverse transform cost about 2e-5 of ||Q||, an
+// FP32 forward transform of the accumulators about half of that.
 template <typename T, int N>
 struct OpLowRank {
   const C<double> *W;
@@ -497,6 +494,47 @@ struct OpGainVss {
   }
 };
 
+// The same pass for the bilinear Q(f, g): Yf and Yg hold the shifted volumes
+// of f and g; the product is Re(u_f u_g) = (t1_f t2_g + t2_f t1_g) / 2, stored
+// (forward along axis 1, planes k1 <= N/2) in Yf.
+template <typename T, int N>
+struct OpGainVss2 {
+  C<T> *Yf;
+  const C<T> *Yg;
+  int M;
+  __device__ void operator()(long v, int r) const {
+    constexpr long n2 = long(N) * N, n3 = n2 * N;
+    C<T> *y = Yf + v * n3 + r;
+    const C<T> *yg = Yg + v * n3 + r;
+    T xr[N], xi[N];
+    {
+      T gr[N], gi[N];
+      static_for<0, N>([&](auto k) {
+        const C<T> e = yg[decltype(k)::value * n2];
+        gr[decltype(k)::value] = e.re;
+        gi[decltype(k)::value] = e.im;
+      });
+      fft_reg<N, +1, T>(gr, gi);
+      static_for<0, N>([&](auto k) {
+        const C<T> e = y[decltype(k)::value * n2];
+        xr[decltype(k)::value] = e.re;
+        xi[decltype(k)::value] = e.im;
+      });
+      fft_reg<N, +1, T>(xr, xi);
+      static_for<0, N>([&](auto j) {
+        constexpr int jj = decltype(j)::value;
+        const T t = xr[jj] * gr[jj] - xi[jj] * gi[jj];
+        xr[jj] = t;
+        xi[jj] = T(0);
+      });
+    }
+    fft_reg<N, -1, T>(xr, xi);
+    static_for<0, N / 2 + 1>([&](auto k) {
+      y[decltype(k)::value * n2] = C<T>{xr[decltype(k)::value], xi[decltype(k)::value]};
+    });
+  }
+};
+
 // Slab accumulation: W[pair] plane k1 (<= N/2) = sum_q alpha_pq(k) fft2(Y[(pair, q)] plane k1)
 // over the (j2, j3) axes.  The M terms of a plane are split in kVssParts fixed
 // parts (blockIdx.y): part 0's sum goes to W, part i's to Wp[i - 1] (launch
@@ -753,9 +791,11 @@ struct Engine {
   // product and back to the spectrum along axis 1, and the weighted slab
   // accumulation over q into the pair's half spectrum W; then the node sum and
   // the half-spectrum tail of the fused schedule.
+  // (Hg, H64g, Yg non-null: the bilinear Q(f, g), two-pass in both precisions)
   static qcoll_status eval_vss(const Plan &p, const C<T> *H, const C<double> *H64, T *A, C<T> *Y, C<double> *TA,
                                C<T> *VP, C<double> *LH, const double *fb, double *Qb, long nb, long pc,
-                               hipStream_t st, const double *isc, int K, long b0) {
+                               hipStream_t st, const double *isc, int K, long b0, const C<T> *Hg = nullptr,
+                               const C<double> *H64g = nullptr, C<T> *Yg = nullptr) {
     constexpr int H1 = N / 2 + 1;
     constexpr long nh = long(H1) * N * N;
     constexpr int SPB = slab_spb2<T, N>();
@@ -764,14 +804,21 @@ struct Engine {
     const T scale = T(1.0 / double(n3));
     qcoll_status s;
     // FP32 with N <= 32: the whole per-pair loop on chip (fused kernel, VSS mode)
-    const bool fused = std::is_same<T, float>::value && use_fused_gain(p);
+    const bool fused = std::is_same<T, float>::value && use_fused_gain(p) && !Hg;
     if (fused && (s = launch_gain_fused(p, H, Wp, nbp, st))) return s;
     for (long bp0 = 0; !fused && bp0 < nbp; bp0 += pc) {
       const long cnt = (nbp - bp0 < pc) ? (nbp - bp0) : pc;
       SrcShift<T, N> src{H, reinterpret_cast<const C<T> *>(p.phase), bp0, p.M, p.N_rho, scale};
       if ((s = slab<SrcShift<T, N>, DstCplx<T, N>, +1>(src, DstCplx<T, N>{Y}, cnt * p.M * N, st, "gain slab")))
         return s;
-      if ((s = pencil(OpGainVss<T, N>{Y, p.M}, cnt * p.M * N * N, st, "vss pencil"))) return s;
+      if (Hg) {
+        SrcShift<T, N> sg{Hg, reinterpret_cast<const C<T> *>(p.phase), bp0, p.M, p.N_rho, scale};
+        if ((s = slab<SrcShift<T, N>, DstCplx<T, N>, +1>(sg, DstCplx<T, N>{Yg}, cnt * p.M * N, st, "gain slab")))
+          return s;
+        if ((s = pencil(OpGainVss2<T, N>{Y, Yg, p.M}, cnt * p.M * N * N, st, "vss pencil"))) return s;
+      } else if ((s = pencil(OpGainVss<T, N>{Y, p.M}, cnt * p.M * N * N, st, "vss pencil"))) {
+        return s;
+      }
       TimedLaunch tl("vss acc", st);
       hipLaunchKernelGGL((k_vss_acc<T, N>), dim3(nblk(cnt * H1, SPB), kVssParts), dim3(SPB * N), 0, st, Y,
                          reinterpret_cast<const T *>(p.alpha_pq), Wp + bp0 * nh, VP, bp0, cnt, p.M, p.N_rho);
@@ -796,8 +843,8 @@ struct Engine {
              SrcCplxHalf<double, N>{TA}, DstCplxHalf<double, N>{TA}, nb * H1, st, "gain inverse slab")))
       return s;
     if ((s = Passes<double, N>::template slab<SrcLossHalf<N>, DstCplxHalf<double, N>, +1>(
-             SrcLossHalf<N>{H64, reinterpret_cast<const double *>(p.lam)}, DstCplxHalf<double, N>{LH}, nb * H1, st,
-             "loss slab")))
+             SrcLossHalf<N>{H64g ? H64g : H64, reinterpret_cast<const double *>(p.lam)}, DstCplxHalf<double, N>{LH},
+             nb * H1, st, "loss slab")))
       return s;
     return pencil(OpAssembleHalf<double, N>{TA, LH, fb, Qb, isc, K, b0}, nb * N * N, st, "assemble");
   }
@@ -879,7 +926,10 @@ struct Engine {
       }
       if constexpr (N <= 48) {   // VSS kernels: N <= 48 (the plan refuses larger grids)
         if (p.is_vss()) {
-          if ((s = eval_vss(p, H, H64, A, Y, TA, VP, LH, fb, Q + b0 * n3, nb, lay.pc, st, isc, K, b0))) return s;
+          if (g && (s = Passes<double, N>::template forward_to<T>(g + b0 * n3, H64g, Hg, nb, st))) return s;
+          if ((s = eval_vss(p, H, H64, A, Y, TA, VP, LH, fb, Q + b0 * n3, nb, lay.pc, st, isc, K, b0,
+                            g ? Hg : nullptr, g ? H64g : nullptr, g ? Yg : nullptr)))
+            return s;
           continue;
         }
       }
@@ -931,12 +981,12 @@ struct Engine {
         QC_LAUNCH_CHECK("mix");
         Bsrc = B;
       }
-      // the low-rank slab pass in FP64 in both precisions (W holds FP64 volumes)
+      // the low-rank stage in FP64 in both precisions (W holds FP64 volumes)
       C<double> *Wd = reinterpret_cast<C<double> *>(W);
       if ((s = Passes<double, N>::template slab<SrcPair<T, N, double>, DstCplx<double, N>, -1>(
                SrcPair<T, N, double>{Bsrc, S, np}, DstCplx<double, N>{Wd}, nb * np * N, st, "low-rank slab")))
         return s;
-      OpLowRank<T, N> lr{Wd, reinterpret_cast<const T *>(p.V), TA, np};
+      OpLowRank<double, N> lr{Wd, p.v64(), TA, np};
       if ((s = pencil(lr, nb * N * N, st, "low-rank pencil"))) return s;
       if ((s = Passes<double, N>::template slab<SrcCplx<double, N>, DstCplx<double, N>, +1>(
                SrcCplx<double, N>{TA}, DstCplx<double, N>{TA}, nb * N, st, "gain inverse slab")))
@@ -1098,8 +1148,10 @@ Layout make_layout(const Plan &p, int64_t batch, int op, long chunk) {
     // items to fill the GPU (32 items at N = 32 in FP64: 1024 workgroups); Y is
     // capped at 4 GiB.
     l.bc = batch < 32 ? (batch > 0 ? batch : 1) : 32;
+    // (VSS kernels add the paired h_pq volumes, ceil(M/2) complex volumes per pair)
     const size_t per_item_y = size_t(p.N_rho) * p.M * n3 * 2 * es;
-    long pc = long((size_t(4) << 30) / per_item_y);
+    const size_t per_item_yh = p.is_vss() ? size_t(p.N_rho) * ((p.M + 1) / 2) * n3 * 2 * es : 0;
+    long pc = long((size_t(4) << 30) / (per_item_y + per_item_yh));
     l.pc = pc < 1 ? 1 : (pc > l.bc ? l.bc : pc);
     if (!use_fused_adjoint(p)) {
       // sub-chunks that fill the accumulation kernel's resident workgroups in
@@ -1129,6 +1181,7 @@ Layout make_layout(const Plan &p, int64_t batch, int op, long chunk) {
     l.off_pm = o; o += al(size_t(l.bc) * kProjSeg * 5 * sizeof(double));
     l.off_dp = o; o += al(size_t(l.bc) * kDomSeg * p.N_rho * sizeof(double));
     l.off_pd = o; o += use_fused_adjoint(p) ? 0 : al(size_t(l.bc) * p.N_rho * p.N * p.N * sizeof(double));
+    l.off_yh = o; o += al(size_t(l.pc) * per_item_yh);
     l.total = o;
     return l;
   }
@@ -1165,7 +1218,7 @@ Layout make_layout(const Plan &p, int64_t batch, int op, long chunk) {
   l.off_y = o; o += (fused || q64) ? 0 : al(size_t(l.pc) * p.M * n3 * 2 * es);
   // two-pass VSS: the partial half spectra of the accumulation's parts 1.. of a launch
   l.off_vp = o;
-  o += (vss && !fused && !bil) ? al(size_t(kVssParts - 1) * l.pc * (p.N / 2 + 1) * p.N * p.N * 2 * es) : 0;
+  o += (vss && !fused) ? al(size_t(kVssParts - 1) * l.pc * (p.N / 2 + 1) * p.N * p.N * 2 * es) : 0;
   if (lit) {
     l.off_yg = o; o += al(size_t(l.pc) * p.M * n3 * 2 * es);   // the Im(beta) volumes
   }

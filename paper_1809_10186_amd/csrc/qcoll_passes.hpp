@@ -47,13 +47,25 @@ constexpr int slab_spb2() {
   return spb_for(N, 2 * N * (N + 1) * int(sizeof(T)));
 }
 
+// resident waves per CU that the LDS tile of a slab block allows (160 KiB per CU)
+constexpr int slab_lds_waves(int N, int spb, int bytes_per_slab) {
+  return (163840 / (spb * bytes_per_slab)) * ((spb * N + 63) / 64);
+}
+
 // k_slab moves one component at a time through LDS (more barriers, half the
 // tile) where that turns blocks with idle lanes into whole waves (N = 48 in
-// FP32), or where both components of one slab exceed 64 KiB (N = 64 in FP64)
+// FP32), where both components of one slab exceed 64 KiB (N = 64 in FP64), or
+// where blocks with idle lanes leave fewer than two waves per SIMD resident and
+// the split tile more (FP64 at N = 24 and 48).  Whole-wave FP64 blocks at
+// N = 32 keep both components: split, their shifted-spectrum slab pass ran
+// slower despite twice the resident waves.
 template <typename T, int N>
 constexpr bool slab_split() {
-  return 2 * N * (N + 1) * int(sizeof(T)) > 65536 ||
-         (lane_use_pct(N, slab_spb2<T, N>()) < 80 && lane_use_pct(N, spb_for(N, N * (N + 1) * int(sizeof(T)))) == 100);
+  constexpr int b2 = 2 * N * (N + 1) * int(sizeof(T)), b1 = N * (N + 1) * int(sizeof(T));
+  constexpr int s2 = slab_spb2<T, N>(), s1 = spb_for(N, b1);
+  return b2 > 65536 || (lane_use_pct(N, s2) < 80 && lane_use_pct(N, s1) == 100) ||
+         (lane_use_pct(N, s2) < 100 && slab_lds_waves(N, s2, b2) < 8 &&
+          slab_lds_waves(N, s1, b1) > slab_lds_waves(N, s2, b2));
 }
 
 template <typename T, int N>
@@ -183,7 +195,13 @@ struct SrcShift {
   int M, Nr;
   T scale;
   __device__ C<T> operator()(long g, int r, int c) const {
-    const long t = g / N;
+    // a slab block never straddles two terms when its slab count divides N
+    // (the N slabs of a term are consecutive and every launch holds whole
+    // terms): the term is then uniform over the wave, and its phase rows are
+    // read with scalar loads instead of one vector load per element
+    constexpr bool UNIFORM = (N % slab_spb<T, N>()) == 0;
+    long t = g / N;
+    if constexpr (UNIFORM) t = __builtin_amdgcn_readfirstlane(int(t));
     const int k1 = int(g % N);
     const long bp = bp0 + t / M;
     const int q = int(t % M);

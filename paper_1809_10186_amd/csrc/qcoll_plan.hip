@@ -131,6 +131,24 @@ bool supported_N(int N) {
   return N == 8 || N == 12 || N == 16 || N == 24 || N == 32 || N == 48 || N == 64;
 }
 
+// d ln(b rho_p^{4-2 omega}) / d omega for every radial node (the omega gradient):
+// d ln b / d omega = ln 2 + psi(2.5 - omega) when b follows omega (the VHS and
+// VSS constants alike), psi by recurrence and the asymptotic series; else 0
+static qcoll_status upload_dlog(Plan &p) {
+  std::vector<double> dl(p.N_rho);
+  double dlb = 0.0;
+  if (p.b_follows_omega) {
+    double x = 2.5 - p.omega, acc = 0.0;
+    while (x < 8.0) { acc -= 1.0 / x; x += 1.0; }
+    const double x2 = 1.0 / (x * x);
+    const double psi = acc + std::log(x) - 0.5 / x -
+                       x2 * (1.0 / 12 - x2 * (1.0 / 120 - x2 * (1.0 / 252 - x2 * (1.0 / 240 - x2 / 132))));
+    dlb = std::log(2.0) + psi;
+  }
+  for (int r = 0; r < p.N_rho; ++r) dl[r] = dlb - 2.0 * std::log(p.rho[r]);
+  return upload<double>(dl, reinterpret_cast<void **>(&p.dlog));
+}
+
 // Kernel tables for the current omega/prefactor (alpha_p rows, Lambda, Lambda_p).
 static void kernel_tables(const Plan &p, std::vector<double> &alpha, std::vector<double> &lam,
                           std::vector<double> &lam_p) {
@@ -223,19 +241,7 @@ static qcoll_status upload_kernel_tables(Plan &p) {
   p.umix = U;
   if ((st = upload_alpha_eff(p, Vs, U)) != QCOLL_OK) return st;
   if ((st = upload<double>(lam_p, reinterpret_cast<void **>(&p.lam_p))) != QCOLL_OK) return st;
-  std::vector<double> dl(m);
-  double dlb = 0.0;
-  if (p.b_follows_omega) {
-    // d ln b / d omega = ln 2 + psi(2.5 - omega); psi by recurrence + asymptotic series
-    double x = 2.5 - p.omega, acc = 0.0;
-    while (x < 8.0) { acc -= 1.0 / x; x += 1.0; }
-    const double x2 = 1.0 / (x * x);
-    const double psi = acc + std::log(x) - 0.5 / x -
-                       x2 * (1.0 / 12 - x2 * (1.0 / 120 - x2 * (1.0 / 252 - x2 * (1.0 / 240 - x2 / 132))));
-    dlb = std::log(2.0) + psi;
-  }
-  for (int r = 0; r < m; ++r) dl[r] = dlb - 2.0 * std::log(p.rho[r]);
-  return upload<double>(dl, reinterpret_cast<void **>(&p.dlog));
+  return upload_dlog(p);
 }
 
 static qcoll_status upload_truncated(Plan &p, int svd_rank, double svd_tol) {
@@ -458,6 +464,9 @@ static qcoll_status upload_vss_tables(Plan &p) {
   p.sigma_max = p.sigma_min_kept = 0.0;
   qcoll_status st;
   if ((st = upload<double>(lam, &p.lam)) != QCOLL_OK) return st;
+  // per-node loss weights and d ln c_p / d omega: the VJP's omega gradient
+  if ((st = upload<double>(lam_p, reinterpret_cast<void **>(&p.lam_p))) != QCOLL_OK) return st;
+  if ((st = upload_dlog(p)) != QCOLL_OK) return st;
   return p.precision == QCOLL_FP32 ? upload<float>(apq, &p.alpha_pq) : upload<double>(apq, &p.alpha_pq);
 }
 

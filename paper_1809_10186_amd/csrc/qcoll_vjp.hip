@@ -147,6 +147,107 @@ struct OpAdjPencil {
   }
 };
 
+// VSS kernels: h_pq = C_pq g differs per sphere point.  Slab pass of the
+// cotangent's weighted spectra, two sphere points per complex volume:
+// alpha_pq0 G + i alpha_pq1 G (slab g = ((pair * MH + qq) * N + k1), MH = ceil(M/2),
+// q0 = 2 qq, q1 = 2 qq + 1 or none), transformed along axes 2 and 3; the adjoint
+// pencil pass inverts it along axis 1 to h_pq0 + i h_pq1 (both real: alpha_pq
+// is even and G Hermitian).  alpha_pq holds the planes k1 <= N/2 (already / N^3);
+// a plane k1 > N/2 reads the reflected index.
+template <typename T, int N>
+struct SrcVssG {
+  const C<T> *G;
+  const T *apq;
+  long bp0;
+  int M, Nr;
+  __device__ C<T> operator()(long g, int r, int c) const {
+    constexpr long n2 = long(N) * N, nh = long(N / 2 + 1) * n2;
+    const int MH = (M + 1) / 2;
+    const long t = g / N;
+    const int k1 = int(g % N);
+    const long bp = bp0 + t / MH;
+    const int qq = int(t % MH);
+    const long b = bp / Nr;
+    const int p = int(bp % Nr);
+    const long o = k1 <= N / 2 ? (long(k1) * N + r) * N + c
+                               : (long(N - k1) * N + (N - r) % N) * N + (N - c) % N;
+    const int q0 = 2 * qq, q1 = 2 * qq + 1;
+    const T a0 = apq[(size_t(p) * M + q0) * nh + o];
+    const T a1 = q1 < M ? apq[(size_t(p) * M + q1) * nh + o] : T(0);
+    const C<T> x = G[b * n2 * N + (long(k1) * N + r) * N + c];
+    return C<T>{a0 * x.re - a1 * x.im, a0 * x.im + a1 * x.re};
+  }
+};
+
+// adjoint pencil pass for VSS kernels: as OpAdjPencil with h_pq (from the
+// paired volumes Yh) in place of w_q h_p (alpha_pq carries w_p w_q).  Where the
+// pencil's four rows (h_pq0, h_pq1 and the term's u) would not fit in the
+// registers (FP64 at N >= 32) the pair's h volume is transformed once per
+// sphere point instead of once per pair.
+template <typename T, int N>
+struct OpAdjPencilVss {
+  C<T> *Y;
+  const C<T> *Yh;
+  double *dots;    // [pairs][N^2] per-pencil parts of sum_q <h_pq, t1 t2>, or null
+  long bp0;
+  int M;
+  static constexpr bool kBothH = sizeof(T) * N < 256;
+  // y = h conj(u) along the pencil, and the pencil's part of <h, Re u^2 - Im u^2>
+  __device__ static T term(C<T> *y, const T (&hv)[N]) {
+    constexpr long n2 = long(N) * N;
+    T xr[N], xi[N];
+    static_for<0, N>([&](auto k) {
+      const C<T> v = y[decltype(k)::value * n2];
+      xr[decltype(k)::value] = v.re;
+      xi[decltype(k)::value] = v.im;
+    });
+    fft_reg<N, +1, T>(xr, xi);
+    T part = T(0);
+    static_for<0, N>([&](auto j) {
+      constexpr int jj = decltype(j)::value;
+      part += hv[jj] * (xr[jj] * xr[jj] - xi[jj] * xi[jj]);
+      xr[jj] = hv[jj] * xr[jj];
+      xi[jj] = -hv[jj] * xi[jj];
+    });
+    fft_reg<N, -1, T>(xr, xi);
+    static_for<0, N>([&](auto k) { y[decltype(k)::value * n2] = C<T>{xr[decltype(k)::value], xi[decltype(k)::value]}; });
+    return part;
+  }
+  __device__ void operator()(long bpl, int r) const {
+    constexpr long n2 = long(N) * N, n3 = n2 * N;
+    const int MH = (M + 1) / 2;
+    double dot = 0.0;
+    for (int qq = 0; qq < MH; ++qq) {
+      const C<T> *yh = Yh + (bpl * MH + qq) * n3 + r;
+      if constexpr (kBothH) {
+        T hr[N], hi[N];
+        static_for<0, N>([&](auto k) {
+          const C<T> v = yh[decltype(k)::value * n2];
+          hr[decltype(k)::value] = v.re;
+          hi[decltype(k)::value] = v.im;
+        });
+        fft_reg<N, +1, T>(hr, hi);
+        dot += double(term(Y + (bpl * M + 2 * qq) * n3 + r, hr));
+        if (2 * qq + 1 < M) dot += double(term(Y + (bpl * M + 2 * qq + 1) * n3 + r, hi));
+      } else {
+        for (int e = 0; e < 2 && 2 * qq + e < M; ++e) {
+          T hr[N], hi[N];
+          static_for<0, N>([&](auto k) {
+            const C<T> v = yh[decltype(k)::value * n2];
+            hr[decltype(k)::value] = v.re;
+            hi[decltype(k)::value] = v.im;
+          });
+          fft_reg<N, +1, T>(hr, hi);
+          T hv[N];
+          static_for<0, N>([&](auto k) { hv[decltype(k)::value] = e ? hi[decltype(k)::value] : hr[decltype(k)::value]; });
+          dot += double(term(Y + (bpl * M + 2 * qq + e) * n3 + r, hv));
+        }
+      }
+    }
+    if (dots) dots[(bp0 + bpl) * n2 + r] = dot;
+  }
+};
+
 // dwg[pair] = sum of the pair's n per-pencil parts, in a fixed order (strided
 // per-thread sums, wave butterflies, then the four waves in order)
 __global__ __launch_bounds__(256) void k_pair_dot_sum(const double *dots, double *dwg, long n) {
@@ -556,6 +657,8 @@ struct Vjp {
     double *pm = reinterpret_cast<double *>(w + lay.off_pm);
     double *dpart = reinterpret_cast<double *>(w + lay.off_dp);
     double *pdots = reinterpret_cast<double *>(w + lay.off_pd);
+    C<T> *Yh = reinterpret_cast<C<T> *>(w + lay.off_yh);     // VSS: paired h_pq volumes of a sub-chunk
+    const bool vss = p.is_vss();
     const int S = p.nv, np = p.npair(), Nr = p.N_rho, M = p.M;
     const bool fused_adjoint = std::is_same<T, float>::value && use_fused_adjoint(p);
     qcoll_status s;
@@ -579,12 +682,13 @@ struct Vjp {
         return s;
       if ((s = P64::pencil(OpPencilInPlace<double, N, -1>{FG64}, nb * N * N, st, "vjp fg pencil"))) return s;
       // h_p = C_p g: packed inverse transforms of (V_2s + i V_2s+1) G^, then unpack + mix
-      if ((s = P::template slab<SrcVPair<T, N>, DstCplx<T, N>, +1>(
-               SrcVPair<T, N>{GT, reinterpret_cast<const T *>(p.V), np}, DstCplx<T, N>{R}, nb * np * N, st,
-               "vjp h slab")))
-        return s;
-      if ((s = P::pencil(OpPencilInPlace<T, N, +1>{R}, nb * np * N * N, st, "vjp h pencil"))) return s;
-      {
+      // (VSS kernels form h_pq per sphere point in the gain loop below instead)
+      if (!vss) {
+        if ((s = P::template slab<SrcVPair<T, N>, DstCplx<T, N>, +1>(
+                 SrcVPair<T, N>{GT, reinterpret_cast<const T *>(p.V), np}, DstCplx<T, N>{R}, nb * np * N, st,
+                 "vjp h slab")))
+          return s;
+        if ((s = P::pencil(OpPencilInPlace<T, N, +1>{R}, nb * np * N * N, st, "vjp h pencil"))) return s;
         TimedLaunch tl("vjp unpack", st);
         launch_unpack_mix<T>(R, reinterpret_cast<const T *>(p.umix_d), Hp, nb, S, Nr, np, n3, st);
         QC_LAUNCH_CHECK("vjp unpack");
@@ -616,10 +720,22 @@ struct Vjp {
           if ((s = P::template slab<SrcShift<T, N>, DstCplx<T, N>, +1>(src, DstCplx<T, N>{Y}, cnt * M * N, st,
                                                                         "vjp gain slab")))
             return s;
-          OpAdjPencil<T, N> op{Y, Hp, reinterpret_cast<const T *>(p.wq), domega ? pdots : nullptr, bp0, M};
-          if ((s = P::pencil(op, cnt * N * N, st, "vjp gain pencil"))) return s;
+          if (vss) {
+            const int MH = (M + 1) / 2;
+            SrcVssG<T, N> sg{GT, reinterpret_cast<const T *>(p.alpha_pq), bp0, M, Nr};
+            if ((s = P::template slab<SrcVssG<T, N>, DstCplx<T, N>, +1>(sg, DstCplx<T, N>{Yh}, cnt * MH * N, st,
+                                                                         "vjp h slab")))
+              return s;
+            OpAdjPencilVss<T, N> op{Y, Yh, domega ? pdots : nullptr, bp0, M};
+            if ((s = P::pencil(op, cnt * N * N, st, "vjp gain pencil"))) return s;
+          } else {
+            OpAdjPencil<T, N> op{Y, Hp, reinterpret_cast<const T *>(p.wq), domega ? pdots : nullptr, bp0, M};
+            if ((s = P::pencil(op, cnt * N * N, st, "vjp gain pencil"))) return s;
+          }
           TimedLaunch tl("vjp gain acc", st);
-          // second half of the tasks into GT (the spectrum of g is no longer needed)
+          // second half of the tasks into the first ni volumes of GT: the spectrum
+          // of g is no longer read for these items (VSS kernels still read it for
+          // the items of later sub-chunks, which lie past the first lay.pc)
           hipLaunchKernelGGL((k_adj_acc<T, N>), dim3(nblk(ni * N, SPB), 2), dim3(SPB * N), 0, st, Y,
                              reinterpret_cast<const C<T> *>(p.phase), Z, GT, ib0, ni, M, Nr);
           hipLaunchKernelGGL((k_adj_acc_add<T>), dim3(nblk(ni * n3, 256)), dim3(256), 0, st, Z + ib0 * n3, GT,

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import kernel, spectral
+from oracle import adjoint, kernel, spectral
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -92,20 +92,105 @@ def test_vss_constant_f_conservation_and_set_omega():
     assert torch.equal(plan.eval(f), fresh.eval(f))
 
 
-def test_vss_refused_operations():
+def test_vss_fused_schedule_request():
     N, L, Nr = 8, 4.0, 4
     plan = qc.Plan(N, L, Nr, sphere=W.sphere_rule(6), omega=0.81, precision=qc.QCOLL_FP32, alpha=1.5)
     f = gpu(W.maxwellian_mixture(1, N, L, 3))
-    with pytest.raises(qc.QcollError) as e:
-        plan.vjp(f, f)
-    assert e.value.code == 2
-    with pytest.raises(qc.QcollError) as e:
-        plan.eval_bilinear(f, f)
-    assert e.value.code == 2
     # the fused schedule has a VSS mode (FP32, N <= 32): requesting it is valid
     plan.set_schedule(2)
-    # the plan still evaluates after the refusals
     assert torch.isfinite(plan.eval(f)).all()
+
+
+# VJP tolerances as for VHS plans: FP64 1e-11, FP32 5e-5 relative to ||df||_inf
+# (the adjoint carries the forward's gain/loss cancellation); d omega 1e-10 / 1e-4
+VJP_TOL = {qc.QCOLL_FP64: (1e-11, 1e-10), qc.QCOLL_FP32: (5e-5, 1e-4)}
+
+
+def _vss_vjp_case(N, L, N_rho, M, batch, alpha, precision, seed):
+    sph = W.sphere_rule(M)
+    f = W.maxwellian_mixture(batch, N, L, seed)
+    g = W.cotangent(f, seed + 1)
+    P = spectral.Params(N, L, N_rho, sph[0], sph[1], 0.81, vss_alpha=alpha)
+    plan = qc.Plan(N, L, N_rho, sphere=sph, omega=0.81, precision=precision, alpha=alpha)
+    df, dw = plan.vjp(gpu(f), gpu(g), want_df=True, want_domega=True)
+    ref = np.stack([adjoint.vjp_f(f[i], g[i], P) for i in range(batch)])
+    refw = np.array([adjoint.vjp_omega(f[i], g[i], P) for i in range(batch)])
+    e = rel(df.cpu().numpy(), ref)
+    ew = float(np.max(np.abs(dw.cpu().numpy() - refw) / np.abs(refw)))
+    return plan, f, g, P, e, ew
+
+
+@pytest.mark.parametrize("precision", [qc.QCOLL_FP64, qc.QCOLL_FP32])
+@pytest.mark.parametrize("N,L,N_rho,M,batch,alpha", [(8, 4.0, 4, 6, 3, 1.5), (12, 5.0, 6, 12, 2, 1.3),
+                                                     (16, 6.0, 8, 12, 2, 1.8)])
+def test_vss_vjp_matches_oracle(N, L, N_rho, M, batch, alpha, precision):
+    """VSS VJP (h_pq = C_pq g per sphere point) against the oracle's adjoint:
+    df and the omega gradient."""
+    print(f"case vss vjp N={N} prec={precision}", flush=True)
+    plan, *_, e, ew = _vss_vjp_case(N, L, N_rho, M, batch, alpha, precision, 4500 + N)
+    print(f"vss vjp N={N} prec={precision}: df rel {e:.3e} domega rel {ew:.3e}", flush=True)
+    assert e <= VJP_TOL[precision][0] and ew <= VJP_TOL[precision][1]
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", [qc.QCOLL_FP64, qc.QCOLL_FP32])
+def test_vss_vjp_32(precision):
+    """32^3 VSS VJP against the oracle (FP64 at 32^3 transforms each sphere
+    point's h volume on its own, FP32 both of a pair's at once), through the
+    conservation projection, and the VJP of a 34-item batch (a full chunk and a
+    ragged one) bit-identical to per-item calls."""
+    N, L, Nr, M, al = 32, 6.0, 6, 6, 1.5
+    print(f"case vss vjp 32^3 prec={precision}", flush=True)
+    plan, f, g, P, e, ew = _vss_vjp_case(N, L, Nr, M, 2, al, precision, 4600)
+    print(f"vss vjp 32^3 prec={precision}: df rel {e:.3e} domega rel {ew:.3e}", flush=True)
+    assert e <= VJP_TOL[precision][0] and ew <= VJP_TOL[precision][1]
+    from oracle import conserve as oc
+    dfp, _ = plan.vjp(gpu(f), gpu(g), through_conserve=True)
+    gp, _ = oc.project(g, N, L)
+    refp = np.stack([adjoint.vjp_f(f[i], gp[i], P) for i in range(2)])
+    ep = rel(dfp.cpu().numpy(), refp)
+    print(f"vss vjp 32^3 through the projection: {ep:.3e}", flush=True)
+    assert ep <= VJP_TOL[precision][0]
+    fb = gpu(W.maxwellian_mixture(34, N, L, 4700))
+    gb = gpu(W.cotangent(fb.cpu().numpy(), 4701))
+    dfb, dwb = plan.vjp(fb, gb, want_domega=True)
+    for i in (0, 17, 33):
+        d1, w1 = plan.vjp(fb[i:i + 1].contiguous(), gb[i:i + 1].contiguous(), want_domega=True)
+        assert torch.equal(d1[0], dfb[i]) and torch.equal(w1[0], dwb[i]), i
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", [qc.QCOLL_FP64, qc.QCOLL_FP32])
+@pytest.mark.parametrize("N,L,N_rho,M,items,alpha", [(8, 4.0, 4, 6, 3, 1.5), (12, 5.0, 6, 12, 2, 1.8)])
+def test_vss_bilinear_matches_oracle(N, L, N_rho, M, items, alpha, precision):
+    """VSS bilinear Q(f, g) (each term's product Re(u_f u_g) weighted by its own
+    alpha_pq) against the oracle; Q(f, f) through it equals qcoll_eval; the
+    paper's U/V DG form with a VSS plan against the literal double sum."""
+    print(f"case vss bilinear N={N} prec={precision}", flush=True)
+    sph = W.sphere_rule(M)
+    f = W.maxwellian_mixture(items, N, L, 2100 + N)
+    g = W.maxwellian_mixture(items, N, L, 2200 + N, T_range=(0.8, 1.6))
+    P = spectral.Params(N, L, N_rho, sph[0], sph[1], 0.81, vss_alpha=alpha)
+    plan = qc.Plan(N, L, N_rho, sphere=sph, omega=0.81, precision=precision, alpha=alpha)
+    Q = plan.eval_bilinear(gpu(f), gpu(g)).cpu().numpy()
+    ref = np.stack([spectral.collide_fg(f[i], g[i], P) for i in range(items)])
+    tol = 1e-12 if precision == qc.QCOLL_FP64 else 2e-5
+    e = rel(Q, ref)
+    Qff = plan.eval_bilinear(gpu(f), gpu(f)).cpu().numpy()
+    e_ff = rel(Qff, plan.eval(gpu(f)).cpu().numpy())
+    print(f"vss bilinear rel {e:.3e}; Q(f, f) through it vs eval {e_ff:.3e}", flush=True)
+    assert e <= tol
+    assert e_ff <= (1e-12 if precision == qc.QCOLL_FP64 else 4e-5)
+    if precision == qc.QCOLL_FP64 and N == 8:
+        from oracle import dg
+        H = dg.triple_tensor_1d(1)
+        T1, T2, Wm = dg.svd_factors(H)
+        F = np.stack([W.maxwellian_mixture(2, N, L, 2300 + e_, noise=0.2) for e_ in range(2)])
+        C = plan.dg_collide_svd(gpu(F), gpu(T1), gpu(T2), gpu(Wm)).cpu().numpy()
+        refd = np.stack([dg.collision_term_direct_bilinear(F[e_], H, P) for e_ in range(2)])
+        ed = np.abs(C - refd).max() / np.abs(refd).max()
+        print(f"vss U/V DG form rel {ed:.3e}", flush=True)
+        assert ed <= 1e-12
 
 
 @pytest.mark.parametrize("N", [24, 32])

@@ -317,6 +317,33 @@ def test_vjp_omega_matches_central_difference():
     assert abs(fd2 - d2) < 1e-7 * abs(d2)
 
 
+@pytest.mark.parametrize("alpha", [1.5, 2.0])
+def test_vss_vjp_matches_central_differences(alpha):
+    """VSS VJP in f: dot-product test against a central difference of Q (exact
+    up to rounding, Q being quadratic); in omega: central difference h = 1e-6;
+    at alpha = 2 both equal the VHS route's."""
+    N, L, om = 6, 4.0, 0.81
+    pts, w = W.sphere_rule(6)
+    P = spectral.Params(N, L, 3, pts, w, om, vss_alpha=alpha)
+    f = W.maxwellian_mixture(1, N, L, 51, noise=0.3)[0]
+    g = W.cotangent(f, 52)
+    v = W.cotangent(f, 53)
+    jtg = adjoint.vjp_f(f, g, P)
+    hf = 1e-3
+    jv = (spectral.collide(f + hf * v, P) - spectral.collide(f - hf * v, P)) / (2 * hf)
+    assert abs(np.sum(g * jv) - np.sum(jtg * v)) < 1e-11 * np.abs(g * jv).sum()
+    d = adjoint.vjp_omega(f, g, P)
+    h = 1e-6
+    Qp = spectral.collide(f, spectral.Params(N, L, 3, pts, w, om + h, vss_alpha=alpha))
+    Qm = spectral.collide(f, spectral.Params(N, L, 3, pts, w, om - h, vss_alpha=alpha))
+    fd = np.sum(g * (Qp - Qm)) / (2 * h)
+    assert abs(fd - d) < 1e-7 * np.abs(g * (Qp - Qm) / (2 * h)).sum()
+    if alpha == 2.0:
+        Pv = spectral.Params(N, L, 3, pts, w, om)
+        assert np.abs(jtg - adjoint.vjp_f(f, g, Pv)).max() < 1e-12 * np.abs(jtg).max()
+        assert abs(d - adjoint.vjp_omega(f, g, Pv)) < 1e-12 * abs(d)
+
+
 def test_digamma_constant():
     # d ln b / d omega at omega = 0.81 is ln 2 + psi(1.69)
     P = params(8, 5.0, 3, omega=0.81)
@@ -421,6 +448,30 @@ def test_bilinear_reduces_to_quadratic_and_matches_direct():
     assert np.abs(Qs - dg.q_sym(f, g, P)).max() < 1e-13 * np.abs(Qs).max()
     # bilinear in each argument
     assert np.abs(spectral.collide_fg(2 * f, 3 * g, P) - 6 * Qfg).max() < 1e-13 * 6 * np.abs(Qfg).max()
+
+
+@pytest.mark.parametrize("alpha", [1.5, 2.0])
+def test_vss_bilinear_reduces_to_quadratic_and_matches_direct(alpha):
+    """VSS bilinear Q(f, g): equals Q(f, f) at g = f, the O(N^6) double sum with
+    the sigma-dependent weights and two spectra, and its symmetric part is the
+    polarisation of the quadratic form; at alpha = 2 it equals the VHS route."""
+    N, L = 6, 4.0
+    pts, w = W.sphere_rule(6)
+    P = spectral.Params(N, L, 3, pts, w, 0.81, vss_alpha=alpha)
+    f = W.maxwellian_mixture(1, N, L, 41, noise=0.2)[0]
+    g = W.maxwellian_mixture(1, N, L, 42, noise=0.2)[0]
+    Qff = spectral.collide(f, P)
+    assert np.abs(spectral.collide_fg(f, f, P) - Qff).max() < 1e-14 * np.abs(Qff).max()
+    Qfg = spectral.collide_fg(f, g, P)
+    Qd = direct.collide_direct(f, P, g=g)
+    assert np.abs(Qfg - Qd).max() < 1e-13 * np.abs(Qd).max()
+    from oracle import dg
+    Qs = 0.5 * (Qfg + spectral.collide_fg(g, f, P))
+    assert np.abs(Qs - dg.q_sym(f, g, P)).max() < 1e-13 * np.abs(Qs).max()
+    if alpha == 2.0:
+        Pv = spectral.Params(N, L, 3, pts, w, 0.81, prefactor=P.kt.b)
+        Qv = spectral.collide_fg(f, g, Pv)
+        assert np.abs(Qfg - Qv).max() < 1e-13 * np.abs(Qv).max()
 
 
 def test_dg_paper_svd_form_equals_double_sum():
