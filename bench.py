@@ -53,6 +53,59 @@ def _oracle_item(args):
     return i, Qc[0]
 
 
+_FFT_CTX = {}
+
+
+def _fft_item(args):
+    """Context worker: the Appendix's formula with numpy.fft (pocketfft, FP64),
+    two inverse transforms per (rho_p, sigma_q) term as the oracle writes it,
+    the oracle's tables, then the conservation projection."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    i, f, prm = args
+    from oracle import spectral
+    from oracle import conserve as oc
+    import workloads as W
+    key = tuple(sorted(prm.items()))
+    if key not in _FFT_CTX:
+        sph = W.sphere_rule(prm["M"])
+        _FFT_CTX[key] = spectral.Params(prm["N"], prm["L"], prm["N_rho"], sph[0], sph[1], prm["omega"],
+                                        svd_tol=prm["svd_tol"])
+    P = _FFT_CTX[key]
+    fft, ifft = np.fft.fftn, np.fft.ifftn
+    X = fft(f)
+    Qh = np.zeros(f.shape, dtype=complex)
+    for p, rho in enumerate(P.kt.rho):
+        A = np.zeros(f.shape, dtype=complex)
+        for q in range(P.M):
+            bt = spectral.beta(P.N, P.L, 0.5 * rho * P.sphere_pts[q], P.nyquist)
+            a = ifft(bt.real * X)
+            b = ifft(bt.imag * X)
+            A += P.sphere_w[q] * (a * a + b * b)
+        Qh += P.alpha[p] * fft(A)
+    Q = (ifft(Qh) - f * ifft(P.lam * X)).real
+    Qc, _ = oc.project(Q[None], prm["N"], prm["L"])
+    return i, Qc[0]
+
+
+def cpu_fft_context(f, prm, ref):
+    """CPU context figure: the same formula with numpy.fft instead of the
+    oracle's DFT matrices, over the items the oracle leg computed, one process
+    per core; also its largest deviation from the oracle."""
+    import multiprocessing as mp
+    cores = min(os.cpu_count() or 1, 16)
+    items = sorted(ref)
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(min(cores, len(items))) as pool:
+        res = dict(pool.map(_fft_item, [(i, f[i], prm) for i in items]))
+    dt = time.perf_counter() - t0
+    dev = max(float(np.abs(res[i] - ref[i]).max() / np.abs(ref[i]).max()) for i in items)
+    return {"value": len(items) / dt, "unit": "evals/s", "cores": min(cores, len(items)),
+            "kind": "numpy.fft FP64, the Appendix's formula (context, not the target)",
+            "sample": f"the {len(items)} items of the oracle leg, {dt:.1f} s wall incl. process start and tables",
+            "max_rel_vs_oracle": dev}
+
+
 def cpu_baseline(f, prm, n_items):
     import multiprocessing as mp
     cores = min(os.cpu_count() or 1, 16)
@@ -353,6 +406,24 @@ def extras(qc, torch, W, reps=3):
     grp.close()
     pl.close()
     del f, Qs
+    out.update(group_uneven(qc, torch, W, reps))
+    return out
+
+
+def group_uneven(qc, torch, W, reps=3):
+    """The uneven three-grid batch through the autotuned group graph (eval with
+    the projection, and the VJP through it), and each branch alone."""
+    def timeit(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3
+
+    out = {}
+    stream = torch.cuda.Stream()
     com = W.UNEVEN_COMMON
     sph = W.sphere_rule(com["M"])
     plans, fs, gs = [], [], []
@@ -451,9 +522,10 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary measurements (DG, VJP, groups)")
     ap.add_argument("--schedule", type=int, default=0, help="hot-loop schedule of the FP32 plan (0 auto)")
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter calibration)")
-    ap.add_argument("--only", choices=("both", "fp32", "fp64", "uneven48"), default="both",
+    ap.add_argument("--only", choices=("both", "fp32", "fp64", "uneven48", "group"), default="both",
                     help="time one path only and print its breakdown (for profiler runs); uneven48: the 48^3 "
-                         "grid of the uneven batch (307 points, FP32 + fix), eval + conserve and the VJP")
+                         "grid of the uneven batch (307 points, FP32 + fix), eval + conserve and the VJP; "
+                         "group: the uneven three-grid batch through the group graph, and each branch alone")
     a = ap.parse_args()
     if a.copy_probe:
         copy_probe()
@@ -469,6 +541,9 @@ def main():
 
     if a.only == "uneven48":
         print(json.dumps(uneven48(qc, torch, W, a.steps, a.warmup)))
+        return
+    if a.only == "group":
+        print(json.dumps(group_uneven(qc, torch, W, reps=a.steps)))
         return
 
     w = W.WORKLOADS[WORKLOAD]
@@ -563,6 +638,7 @@ def main():
         n_cpu = a.cpu_items or min(12 * min(os.cpu_count() or 1, 16), B)
         prm = dict(N=N, L=L, N_rho=Nr, M=M, omega=w["omega"], svd_tol=w["svd_tol"])
         cpu, ref = cpu_baseline(f_np[:max(n_cpu, 1)], prm, n_cpu) if not a.no_cpu else (None, {})
+        fft_ctx = cpu_fft_context(f_np, prm, ref) if ref else None
         if not a.no_acc:
             from oracle import spectral
             from oracle import conserve as oc
@@ -608,6 +684,7 @@ def main():
         "roofline_fp64": roof64,
         "secondary": extra,
         "cpu_baseline": cpu,
+        "cpu_fft_context": fft_ctx,
     }
     print(json.dumps(out))
 

@@ -129,11 +129,13 @@ typedef struct {
 /* Validate parameters without touching any device.  QCOLL_OK, EINVAL or ENOTSUP. */
 qcoll_status qcoll_params_check(const qcoll_params *p);
 
-/* Build a plan on the current HIP device: quadratures, kernel-mode tables
- * (Appendix, quadrature form of G), per-axis shift tables, optional SVD, all
- * in FP64 on the host, then copied to device memory owned by the plan.
- * *out is set only on success. */
-qcoll_status qcoll_plan_create(const qcoll_params *p, qcoll_plan *out);
+/* Build a plan on HIP device `device` (< 0: the current device): quadratures,
+ * kernel-mode tables (Appendix, quadrature form of G), per-axis shift tables,
+ * optional SVD, all in FP64 on the host, then copied to device memory owned by
+ * the plan.  The caller's current device is left as it was.  Every later call
+ * with the plan must run with that device current (EINVAL otherwise).
+ * *out is set only on success; EINVAL for a device index out of range. */
+qcoll_status qcoll_plan_create(const qcoll_params *p, int32_t device, qcoll_plan *out);
 
 /* Free the plan and its device tables.  The caller must have synchronised
  * every stream that used it.  NULL is accepted. */

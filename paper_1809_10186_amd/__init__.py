@@ -68,7 +68,7 @@ def lib():
         vp, i64, i32, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
         sig = {
             "qcoll_params_check": ([ctypes.POINTER(Params)], i32),
-            "qcoll_plan_create": ([ctypes.POINTER(Params), ctypes.POINTER(vp)], i32),
+            "qcoll_plan_create": ([ctypes.POINTER(Params), i32, ctypes.POINTER(vp)], i32),
             "qcoll_plan_destroy": ([vp], i32),
             "qcoll_plan_info": ([vp, ctypes.POINTER(PlanInfo)], i32),
             "qcoll_plan_radial": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], i32),
@@ -200,8 +200,7 @@ class Plan:
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         p, keep = make_params(N, L, N_rho, sphere, omega, prefactor, svd_rank, svd_tol, precision, alpha, nyquist)
         h = ctypes.c_void_p()
-        with torch.cuda.device(self.device):
-            _check(lib().qcoll_plan_create(ctypes.byref(p), ctypes.byref(h)))
+        _check(lib().qcoll_plan_create(ctypes.byref(p), self.device.index, ctypes.byref(h)))
         del keep
         self._h = h
         self.N, self.L, self.N_rho = int(N), float(L), int(N_rho)

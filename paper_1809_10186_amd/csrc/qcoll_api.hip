@@ -120,10 +120,26 @@ qcoll_status qcoll_params_check(const qcoll_params *p) {
   return QCOLL_OK;
 }
 
-qcoll_status qcoll_plan_create(const qcoll_params *prm, qcoll_plan *out) {
+qcoll_status qcoll_plan_create(const qcoll_params *prm, int32_t device, qcoll_plan *out) {
   if (!out) return fail(QCOLL_EINVAL, "out is NULL");
   qcoll_status st = qcoll_params_check(prm);
   if (st != QCOLL_OK) return st;
+  int prev = -1, ndev = 0;
+  if (hipGetDevice(&prev) != hipSuccess || hipGetDeviceCount(&ndev) != hipSuccess)
+    return fail(QCOLL_EDEVICE, "no HIP device");
+  if (device >= ndev) return fail(QCOLL_EINVAL, "device index out of range");
+  // build with the requested device current, then give the caller back its own
+  struct Restore {
+    int dev;
+    bool on;
+    ~Restore() {
+      if (on) (void)hipSetDevice(dev);
+    }
+  } restore{prev, device >= 0 && device != prev};
+  if (restore.on && hipSetDevice(device) != hipSuccess) {
+    restore.on = false;
+    return fail(QCOLL_EDEVICE, "hipSetDevice failed");
+  }
   auto *h = new (std::nothrow) qcoll_plan_s;
   if (!h) return fail(QCOLL_ENOMEM, "host allocation failed");
   st = qcoll::plan_build(h->p, *prm);

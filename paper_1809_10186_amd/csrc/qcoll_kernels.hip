@@ -1006,7 +1006,12 @@ struct Engine {
 // FP64 conservation projection: one 1024-lane workgroup per item.  Each lane
 // walks pairs of consecutive points along the last axis (16-byte loads); the
 // velocity of a point is rebuilt from its index.  The five sums are reduced
-// in a fixed order, so the result is deterministic.
+// in a fixed order, so the result is deterministic.  With PPT > 0 (grids up
+// to 32^3: at most 16 pairs per lane) a lane keeps its PPT pairs in registers
+// between the sums and the correction, so Q is read once; PPT = 0 reads it
+// twice.  Both visit a lane's pairs in the same order: the results are
+// bit-identical.
+template <int PPT>
 __global__ __launch_bounds__(1024) void k_conserve(double *Q, double *mom, const double *ginv, int N, double L,
                                                    int *flag, double dc3, const double *isc, int K) {
   const long n3 = long(N) * N * N;
@@ -1014,13 +1019,18 @@ __global__ __launch_bounds__(1024) void k_conserve(double *Q, double *mom, const
   double2 *q = reinterpret_cast<double2 *>(Q + b * n3);
   const double dc = 2.0 * L / N;
   const long nh = n3 / 2;   // N is even: a pair never crosses a row
-  double s[5] = {0, 0, 0, 0, 0};
-  for (long h = threadIdx.x; h < nh; h += blockDim.x) {
+  auto coords = [&](long h, double &c1, double &c2, double &c3a, double &c3b) {
     const long j = 2 * h;
     const int i1 = int(j / (N * N)), i2 = int((j / N) % N), i3 = int(j % N);
-    const double c1 = -L + (i1 + 0.5) * dc, c2 = -L + (i2 + 0.5) * dc;
-    const double c3a = -L + (i3 + 0.5) * dc, c3b = c3a + dc;
-    const double2 v = q[h];
+    c1 = -L + (i1 + 0.5) * dc;
+    c2 = -L + (i2 + 0.5) * dc;
+    c3a = -L + (i3 + 0.5) * dc;
+    c3b = c3a + dc;
+  };
+  double s[5] = {0, 0, 0, 0, 0};
+  auto add = [&](long h, double2 v) {
+    double c1, c2, c3a, c3b;
+    coords(h, c1, c2, c3a, c3b);
     const double sv = v.x + v.y;
     const double r12 = c1 * c1 + c2 * c2;
     s[0] += sv;
@@ -1028,6 +1038,19 @@ __global__ __launch_bounds__(1024) void k_conserve(double *Q, double *mom, const
     s[2] += sv * c2;
     s[3] += v.x * c3a + v.y * c3b;
     s[4] += v.x * (r12 + c3a * c3a) + v.y * (r12 + c3b * c3b);
+  };
+  double2 keep[PPT > 0 ? PPT : 1];
+  if constexpr (PPT > 0) {
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const long h = threadIdx.x + long(i) * blockDim.x;
+      if (h < nh) {
+        keep[i] = q[h];
+        add(h, keep[i]);
+      }
+    }
+  } else {
+    for (long h = threadIdx.x; h < nh; h += blockDim.x) add(h, q[h]);
   }
   __shared__ double red[5][1024];
   for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = s[k];
@@ -1052,18 +1075,24 @@ __global__ __launch_bounds__(1024) void k_conserve(double *Q, double *mom, const
       for (int k = 0; k < 5; ++k) mom[b * 5 + k] = m[k] * dc3;
     if (!finite) atomicOr(flag, 1);
   }
-  for (long h = threadIdx.x; h < nh; h += blockDim.x) {
-    const long j = 2 * h;
-    const int i1 = int(j / (N * N)), i2 = int((j / N) % N), i3 = int(j % N);
-    const double c1 = -L + (i1 + 0.5) * dc, c2 = -L + (i2 + 0.5) * dc;
-    const double c3a = -L + (i3 + 0.5) * dc, c3b = c3a + dc;
+  auto fix = [&](long h, double2 v) {
+    double c1, c2, c3a, c3b;
+    coords(h, c1, c2, c3a, c3b);
     const double base = lam[0] + lam[1] * c1 + lam[2] * c2 + lam[4] * (c1 * c1 + c2 * c2);
-    double2 v = q[h];
     v.x -= base + lam[3] * c3a + lam[4] * c3a * c3a;
     v.y -= base + lam[3] * c3b + lam[4] * c3b * c3b;
     v.x *= sc;
     v.y *= sc;
     q[h] = v;
+  };
+  if constexpr (PPT > 0) {
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const long h = threadIdx.x + long(i) * blockDim.x;
+      if (h < nh) fix(h, keep[i]);
+    }
+  } else {
+    for (long h = threadIdx.x; h < nh; h += blockDim.x) fix(h, q[h]);
   }
 }
 
@@ -1262,8 +1291,19 @@ qcoll_status launch_conserve(const Plan &p, int64_t batch, double *Q, double *mo
                              int K) {
   const double dc = 2.0 * p.L / p.N;
   TimedLaunch tl("conserve", st);
-  hipLaunchKernelGGL(k_conserve, dim3(unsigned(batch)), dim3(1024), 0, st, Q, mom, p.ginv, p.N, p.L, p.flag,
-                     dc * dc * dc, isc, K);
+  // pairs per lane of the register-resident variant: N^3 / 2 / 1024, rounded up
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(unsigned(batch)), dim3(1024), 0, st, Q, mom, p.ginv, p.N, p.L, p.flag,
+                       dc * dc * dc, isc, K);
+  };
+  switch (p.N) {
+    case 8:
+    case 12: go(k_conserve<1>); break;
+    case 16: go(k_conserve<2>); break;
+    case 24: go(k_conserve<7>); break;
+    case 32: go(k_conserve<16>); break;
+    default: go(k_conserve<0>); break;
+  }
   QC_LAUNCH_CHECK("conserve");
   return QCOLL_OK;
 }

@@ -104,7 +104,9 @@ static void check_params() {
 
 static void check_plan(const qcoll_params &prm) {
   qcoll_plan plan = nullptr;
-  EXPECT(qcoll_plan_create(&prm, &plan) == QCOLL_OK);
+  qcoll_plan bad = nullptr;
+  EXPECT(qcoll_plan_create(&prm, 1 << 20, &bad) == QCOLL_EINVAL && bad == nullptr);
+  EXPECT(qcoll_plan_create(&prm, -1, &plan) == QCOLL_OK);
   if (!plan) return;
   qcoll_plan_info_t info;
   EXPECT(qcoll_plan_info(plan, &info) == QCOLL_OK);
@@ -160,7 +162,7 @@ static void check_autotune_cache(const char *path) {
   qcoll_params prm = base(8);
   prm.precision = QCOLL_FP32;
   qcoll_plan plan = nullptr;
-  EXPECT(qcoll_plan_create(&prm, &plan) == QCOLL_OK);
+  EXPECT(qcoll_plan_create(&prm, -1, &plan) == QCOLL_OK);
   if (!plan) return;
   // malformed and hostile lines around one valid entry for this plan's key
   FILE *fp = std::fopen(path, "w");

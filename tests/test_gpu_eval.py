@@ -122,6 +122,21 @@ def test_nonfinite_input_is_flagged():
     plan.poll()   # flag cleared
 
 
+def test_plan_device_argument():
+    """qcoll_plan_create on an explicit device index, and EINVAL for one past
+    the device count (the caller's current device is left as it was)."""
+    N = 8
+    cur = torch.cuda.current_device()
+    plan = qc.Plan(N, 4.0, 4, sphere=None, omega=0.81, device=cur)
+    f = torch.ones((1, N, N, N), dtype=torch.float64, device="cuda")
+    assert torch.isfinite(plan.eval(f)).all()
+    plan.close()
+    with pytest.raises(qc.QcollError) as e:
+        qc.Plan(N, 4.0, 4, sphere=None, omega=0.81, device=torch.cuda.device_count())
+    assert e.value.code == 1
+    assert torch.cuda.current_device() == cur
+
+
 def test_error_paths_on_device():
     N = 8
     plan = qc.Plan(N, 4.0, 4, sphere=None, omega=0.81)
