@@ -21,6 +21,11 @@
 // to the forward spectrum in lane (k2, k3).  The partner values P(-k) sit in
 // lane (-k2, -k3); every lane puts the N/2 + 1 values its partner needs into
 // LDS (the transpose tile is free at that point) and reads its own.
+//
+// h_p = C_p g = ifft3[alpha_p g^] is formed by the workgroup itself before the
+// term loop: the same three inverse stages on alpha_p g^ leave lane (j1, j2)
+// with the row h_p(j1, j2, :), which it stores to the pair's scratch volume and
+// re-reads (its own row, from L2) in every term.
 #include <hip/hip_runtime.h>
 
 #include "qcoll_fused.hpp"
@@ -43,13 +48,16 @@ struct AdjGeom {
   static size_t lds_bytes(int M) { return (work + size_t(2) * M * N) * sizeof(float); }
 };
 
-// H: FP32 spectra of the items [item][N^3]; Hp: h_p = C_p g, [pair][N^3] real;
-// Zh: per-pair half spectra [pair][N/2 + 1][N^2]; dwg: [pair] <h_p, A_p> (DW).
+// H, Gs: FP32 spectra of the items' f and g [item][N^3]; alpha: the plan's
+// effective per-node gain weights [N_rho][N^3] (already / N^3); Hp: scratch
+// for h_p, [pair][N^3] real, written and read by the pair's workgroup; Zh:
+// per-pair half spectra [pair][N/2 + 1][N^2]; dwg: [pair] <h_p, A_p> (DW).
 template <int N, bool DW>
 __global__ __launch_bounds__(FusedGeom<N>::NL) void k_adj_fused(const cplx<float> *__restrict__ H,
+                                                                const cplx<float> *__restrict__ Gs,
                                                                 const cplx<float> *__restrict__ phase,
                                                                 const float *__restrict__ wq,
-                                                                const float *__restrict__ Hp,
+                                                                const float *__restrict__ alpha, float *Hp,
                                                                 cplx<float> *__restrict__ Zh, double *dwg, long nbp,
                                                                 int M, int Nr, float scale) {
   using G = FusedGeom<N>;
@@ -75,10 +83,6 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_adj_fused(const cplx<float
   // the lane holding pencil (-k2, -k3) in the spectral layout
   const int partner = ((N - hi) % N) * N + (N - lo) % N;
 
-  float acc[2 * H1];
-  static_for<0, 2 * H1>([&](auto j) { acc[decltype(j)::value] = 0.f; });
-  double dot = 0.0;
-
   auto wa1 = [&](int, int i) { return i * S1 + hi * N + lo; };
   auto ra1 = [&](int, int i) { return hi * S1 + i * N + lo; };
   auto wa2 = [&](int, int i) { return hi * S1 + lo * (N + 1) + i; };
@@ -88,6 +92,41 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_adj_fused(const cplx<float
     if constexpr (G::WAVE_BC) lds_transpose_wave<N, 1>(lds, v, wa, ra);
     else lds_transpose<N, 1>(lds, v, wa, ra);
   };
+
+  {
+    // h_p: lane (k2, k3) loads alpha_p g^ along k1, inverse along axes 1, 2, 3
+    // with the term loop's transposes, then lane (j1, j2) stores its row
+    float zr[1][N], zi[1][N];
+    const __amdgpu_buffer_rsrc_t gr = make_rsrc(Gs + b * n3, unsigned(n3 * sizeof(cplx<float>)));
+    const float *al = alpha + size_t(p) * n3 + lane;
+    static_for<0, N>([&](auto k) {
+      constexpr int kk = decltype(k)::value;
+      const cplx<float> v = load_c32(gr, int(lane * sizeof(cplx<float>)), int(kk * n2 * sizeof(cplx<float>)));
+      const float a = al[kk * n2];
+      zr[0][kk] = v.re * a;
+      zi[0][kk] = v.im * a;
+    });
+    fft_reg<N, +1, float>(zr[0], zi[0]);
+    lds_transpose<N, 1>(lds, zr, wa1, ra1);
+    lds_transpose<N, 1>(lds, zi, wa1, ra1);
+    fft_reg<N, +1, float>(zr[0], zi[0]);
+    transpose_bc(zr, wa2, ra2);
+    transpose_bc(zi, wa2, ra2);
+    fft_reg<N, +1, float>(zr[0], zi[0]);
+    // h_p is real (alpha_p even and real, g real): keep the real part
+    float *ho = Hp + bp * n3 + long(lane) * N;
+    static_for<0, N / 4>([&](auto v4) {
+      constexpr int j0 = 4 * decltype(v4)::value;
+      *reinterpret_cast<float4 *>(ho + j0) = float4{zr[0][j0], zr[0][j0 + 1], zr[0][j0 + 2], zr[0][j0 + 3]};
+    });
+    // the term loop re-reads the row through a buffer descriptor the compiler
+    // does not tie to these stores: complete them first
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  }
+
+  float acc[2 * H1];
+  static_for<0, 2 * H1>([&](auto j) { acc[decltype(j)::value] = 0.f; });
+  double dot = 0.0;
 
   const __amdgpu_buffer_rsrc_t hr = make_rsrc(H + b * n3, unsigned(n3 * sizeof(cplx<float>)));
   // h_p through a buffer descriptor, re-read for every q where it is used
@@ -204,8 +243,8 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_adj_fused(const cplx<float
 }
 
 template <int N, bool DW>
-static qcoll_status launch_adj(const Plan &p, const cplx<float> *H, const float *Hp, cplx<float> *Zh, double *dwg,
-                               long nbp, hipStream_t st) {
+static qcoll_status launch_adj(const Plan &p, const cplx<float> *H, const cplx<float> *G, float *Hp,
+                               cplx<float> *Zh, double *dwg, long nbp, hipStream_t st) {
   using A = AdjGeom<N>;
   const size_t lds = A::lds_bytes(p.M);
   if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_adj_fused<N, DW>),
@@ -215,9 +254,9 @@ static qcoll_status launch_adj(const Plan &p, const cplx<float> *H, const float 
   }
   TimedLaunch tl("vjp adjoint fused", st);
   const float scale = float(1.0 / double(long(N) * N * N));
-  hipLaunchKernelGGL((k_adj_fused<N, DW>), dim3(unsigned(nbp)), dim3(FusedGeom<N>::NL), lds, st, H,
-                     reinterpret_cast<const cplx<float> *>(p.phase), reinterpret_cast<const float *>(p.wq), Hp, Zh,
-                     dwg, nbp, p.M, p.N_rho, scale);
+  hipLaunchKernelGGL((k_adj_fused<N, DW>), dim3(unsigned(nbp)), dim3(FusedGeom<N>::NL), lds, st, H, G,
+                     reinterpret_cast<const cplx<float> *>(p.phase), reinterpret_cast<const float *>(p.wq),
+                     reinterpret_cast<const float *>(p.alpha_eff), Hp, Zh, dwg, nbp, p.M, p.N_rho, scale);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     set_error(std::string("vjp adjoint fused: ") + hipGetErrorString(e));
@@ -227,9 +266,10 @@ static qcoll_status launch_adj(const Plan &p, const cplx<float> *H, const float 
 }
 
 template <int N>
-static qcoll_status launch_adj_any(const Plan &p, const cplx<float> *H, const float *Hp, cplx<float> *Zh,
-                                   double *dwg, long nbp, hipStream_t st) {
-  return dwg ? launch_adj<N, true>(p, H, Hp, Zh, dwg, nbp, st) : launch_adj<N, false>(p, H, Hp, Zh, dwg, nbp, st);
+static qcoll_status launch_adj_any(const Plan &p, const cplx<float> *H, const cplx<float> *G, float *Hp,
+                                   cplx<float> *Zh, double *dwg, long nbp, hipStream_t st) {
+  return dwg ? launch_adj<N, true>(p, H, G, Hp, Zh, dwg, nbp, st)
+             : launch_adj<N, false>(p, H, G, Hp, Zh, dwg, nbp, st);
 }
 
 static size_t adj_lds_bytes(int N, int M) {
@@ -250,16 +290,17 @@ bool use_fused_adjoint(const Plan &p) {
          adj_lds_bytes(p.N, p.M) <= size_t(160) * 1024;
 }
 
-qcoll_status launch_adjoint_fused(const Plan &p, const void *H, const float *Hp, void *Zh, double *dwg, long nbp,
-                                  hipStream_t st) {
+qcoll_status launch_adjoint_fused(const Plan &p, const void *H, const void *G, float *Hp, void *Zh, double *dwg,
+                                  long nbp, hipStream_t st) {
   const auto *h = static_cast<const cplx<float> *>(H);
+  const auto *g = static_cast<const cplx<float> *>(G);
   auto *z = static_cast<cplx<float> *>(Zh);
   switch (p.N) {
-    case 8: return launch_adj_any<8>(p, h, Hp, z, dwg, nbp, st);
-    case 12: return launch_adj_any<12>(p, h, Hp, z, dwg, nbp, st);
-    case 16: return launch_adj_any<16>(p, h, Hp, z, dwg, nbp, st);
-    case 24: return launch_adj_any<24>(p, h, Hp, z, dwg, nbp, st);
-    case 32: return launch_adj_any<32>(p, h, Hp, z, dwg, nbp, st);
+    case 8: return launch_adj_any<8>(p, h, g, Hp, z, dwg, nbp, st);
+    case 12: return launch_adj_any<12>(p, h, g, Hp, z, dwg, nbp, st);
+    case 16: return launch_adj_any<16>(p, h, g, Hp, z, dwg, nbp, st);
+    case 24: return launch_adj_any<24>(p, h, g, Hp, z, dwg, nbp, st);
+    case 32: return launch_adj_any<32>(p, h, g, Hp, z, dwg, nbp, st);
     default: set_error("fused adjoint kernel: unsupported N"); return QCOLL_ENOTSUP;
   }
 }

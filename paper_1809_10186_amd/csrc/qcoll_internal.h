@@ -119,8 +119,9 @@ bool use_fused_adjoint(const Plan &p);
 // two-pass VJP: the largest item count whose adjoint accumulation launch fits
 // the device's resident workgroups in one round (0 if the query fails)
 long adj_acc_items_per_round(const Plan &p);
-qcoll_status launch_adjoint_fused(const Plan &p, const void *H, const float *Hp, void *Zh, double *dwg, long nbp,
-                                  hipStream_t st);
+// H, G: FP32 spectra of f and g; Hp: scratch for h_p = C_p g (formed on chip)
+qcoll_status launch_adjoint_fused(const Plan &p, const void *H, const void *G, float *Hp, void *Zh, double *dwg,
+                                  long nbp, hipStream_t st);
 
 // kernel timing (hipEvents on the launch stream) for roofline accounting
 bool timing_on();

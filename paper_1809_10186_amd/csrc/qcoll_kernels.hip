@@ -1176,7 +1176,10 @@ Layout make_layout(const Plan &p, int64_t batch, int op, long chunk) {
     // group of slabs of the sub-chunk's items, so the sub-chunk must hold enough
     // items to fill the GPU (32 items at N = 32 in FP64: 1024 workgroups); Y is
     // capped at 4 GiB.
-    l.bc = batch < 32 ? (batch > 0 ? batch : 1) : 32;
+    // The fused adjoint has no sub-chunks: its chunks hold up to 256 items
+    // (fewer, larger launches of the small passes around it).
+    const long cap = use_fused_adjoint(p) ? 256 : 32;
+    l.bc = batch < cap ? (batch > 0 ? batch : 1) : cap;
     // (VSS kernels add the paired h_pq volumes, ceil(M/2) complex volumes per pair)
     const size_t per_item_y = size_t(p.N_rho) * p.M * n3 * 2 * es;
     const size_t per_item_yh = p.is_vss() ? size_t(p.N_rho) * ((p.M + 1) / 2) * n3 * 2 * es : 0;

@@ -682,8 +682,9 @@ struct Vjp {
         return s;
       if ((s = P64::pencil(OpPencilInPlace<double, N, -1>{FG64}, nb * N * N, st, "vjp fg pencil"))) return s;
       // h_p = C_p g: packed inverse transforms of (V_2s + i V_2s+1) G^, then unpack + mix
-      // (VSS kernels form h_pq per sphere point in the gain loop below instead)
-      if (!vss) {
+      // (the fused adjoint forms h_p on chip; VSS kernels form h_pq per sphere
+      // point in the gain loop below)
+      if (!vss && !fused_adjoint) {
         if ((s = P::template slab<SrcVPair<T, N>, DstCplx<T, N>, +1>(
                  SrcVPair<T, N>{GT, reinterpret_cast<const T *>(p.V), np}, DstCplx<T, N>{R}, nb * np * N, st,
                  "vjp h slab")))
@@ -698,7 +699,7 @@ struct Vjp {
         // over p of the pairs' half spectra and the inverse along axes 2, 3
         constexpr int H1 = N / 2 + 1;
         constexpr long nh = long(H1) * N * N;
-        if ((s = launch_adjoint_fused(p, H, reinterpret_cast<const float *>(Hp), Y, domega ? dwg : nullptr,
+        if ((s = launch_adjoint_fused(p, H, GT, reinterpret_cast<float *>(Hp), Y, domega ? dwg : nullptr,
                                       nb * Nr, st)))
           return s;
         {
