@@ -140,12 +140,13 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_adj_fused(const cplx<float
     const float xr = b2.re * b3.re - b2.im * b3.im;
     const float yi = b2.re * b3.im + b2.im * b3.re;
     const float Pm = xr + yi, Qm = xr - yi;
+    const float Ps = Pm * scale, Qs = Qm * scale;   // the inverse's 1/N^3, once per term
     const cplx<float> *b1q = b1s + q * N;
     static_for<0, N>([&](auto k) {
       constexpr int kk = decltype(k)::value;
       const cplx<float> v = load_c32(hr, int(lane * sizeof(cplx<float>)), int(kk * n2 * sizeof(cplx<float>)));
       const cplx<float> b1 = b1q[kk];
-      const float c = (b1.re * Pm + b1.im * Qm) * scale;
+      const float c = b1.re * Ps + b1.im * Qs;
       zr[0][kk] = v.re * c;
       zi[0][kk] = v.im * c;
     });

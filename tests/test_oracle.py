@@ -723,3 +723,26 @@ def test_kernel_table_truncation_closed_form():
     assert rank == 2 and np.abs(At.reshape(m, -1) - (U[:, :2] * s[:2]) @ V[:, :2].T).max() <= 1e-12 * 10
     At, rank = kernel.truncate_alpha(alpha, svd_rank=m)
     assert rank == m and np.abs(At - alpha).max() <= 1e-13 * 10
+
+
+def test_vss_joint_weight_table_is_nearly_full_rank():
+    """Why VSS plans keep the full alpha_pq table (no SVD over (p, q)): a rank-r
+    factorisation alpha_pq = sum_s U[pq, s] V_s would replace the N_rho*M
+    forward transforms per item by r, at the price of mixing the N_rho*M
+    products into r sums, r*N_rho*M multiply-adds per point.  The joint table
+    of a VSS kernel keeps most of its rank (here 79 of 96 at 1e-8, 66 at 1e-4;
+    163 of 192 at the 1D DG batch's grid), and every radial node but the first
+    keeps full rank over q, so the mixing (r*N_rho*M ~ 7.6e3 flops per point)
+    costs far more than the 17 transforms it saves (5 log2(N^3) = 60 flops per
+    point each, ~1.0e3 in all)."""
+    N, L, Nr, M = 16, 6.0, 8, 12
+    sph = W.sphere_rule(M)
+    P = spectral.Params(N, L, Nr, sph[0], sph[1], 0.81, vss_alpha=1.5)
+    s = np.linalg.svd(P.alpha_pq.reshape(Nr * M, -1), compute_uv=False)
+    r8, r4 = int((s > 1e-8 * s[0]).sum()), int((s > 1e-4 * s[0]).sum())
+    assert r8 >= 0.8 * Nr * M and r4 >= 0.65 * Nr * M
+    for p in range(1, Nr):
+        sp = np.linalg.svd(P.alpha_pq[p].reshape(M, -1), compute_uv=False)
+        assert int((sp > 1e-8 * s[0]).sum()) == M
+    saved = Nr * M - r8
+    assert r8 * Nr * M > 5 * saved * 5 * np.log2(N ** 3)
