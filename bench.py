@@ -633,6 +633,7 @@ def main():
 
     acc = None
     cpu = None
+    fft_ctx = None
     if not a.no_acc or not a.no_cpu:
         # about 10-20 s of oracle work: 12 items per host core (one item ~1 s), at most the batch
         n_cpu = a.cpu_items or min(12 * min(os.cpu_count() or 1, 16), B)
