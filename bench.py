@@ -269,6 +269,29 @@ def copy_probe(mib=1024, reps=5):
     print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "reps": reps}))
 
 
+def stream_probe(mib=1024, reps=20):
+    """Achievable HBM rates on this device: a 1 GiB copy (read + write), a
+    1 GiB fill (write only) and a 1 GiB sum (read only), timed with events."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    out = {}
+    for name, fn, nbytes in (("copy", lambda: b.copy_(a), 8 * n), ("fill", lambda: b.fill_(1.5), 4 * n),
+                             ("read", lambda: a.sum(), 4 * n)):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": round(ms, 4), "GB_per_s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+    print(json.dumps({"stream_probe_MiB": mib, **out}))
+
+
 def extras(qc, torch, W, reps=3):
     """Secondary measurements of the rows outside the headline step, each on its
     own synthetic workload: the DG weak-form term with the MFMA contractions,
@@ -522,6 +545,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary measurements (DG, VJP, groups)")
     ap.add_argument("--schedule", type=int, default=0, help="hot-loop schedule of the FP32 plan (0 auto)")
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="only time a 1 GiB copy, fill and sum (achievable HBM rates)")
     ap.add_argument("--only", choices=("both", "fp32", "fp64", "uneven48", "group"), default="both",
                     help="time one path only and print its breakdown (for profiler runs); uneven48: the 48^3 "
                          "grid of the uneven batch (307 points, FP32 + fix), eval + conserve and the VJP; "
@@ -529,6 +554,9 @@ def main():
     a = ap.parse_args()
     if a.copy_probe:
         copy_probe()
+        return
+    if a.stream_probe:
+        stream_probe()
         return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: every item is independent and the box has one GPU; "
