@@ -169,7 +169,9 @@ def test_error_paths_on_device():
 
 def test_dg1d_full_size_sampled_items():
     """The 1D DG batch at full size (192 items, 32^3, M=12, N_rho=16, omega 0.81,
-    SVD at 1e-8), in the bench's launch configuration; sampled items vs oracle."""
+    SVD at 1e-8) with the plan's default chunk (64 items: three chunks); three
+    sampled items vs oracle.  Every item in the bench's autotuned launch
+    configuration is checked in test_gpu_fullsize."""
     w = W.WORKLOADS["dg1d_32"]
     N, L = w["N"], w["L"]
     f = W.mixture_for("dg1d_32")
