@@ -144,3 +144,31 @@ def test_group_graph_recaptured_after_plan_changes():
     pb.set_chunk(4)
     check()
     grp.close()
+
+
+def test_group_with_vss_plan_eval_and_vjp():
+    """A group of a VHS plan and a VSS plan (alpha = 1.5, two-pass adjoint):
+    group eval and group VJP (eager and through the graph) equal the per-plan
+    calls bit for bit."""
+    sph = W.sphere_rule(12)
+    pa = qc.Plan(16, 6.0, 8, sphere=sph, omega=0.81, precision=qc.QCOLL_FP32)
+    pv = qc.Plan(12, 5.0, 6, sphere=sph, omega=0.81, precision=qc.QCOLL_FP64, alpha=1.5)
+    fa = W.maxwellian_mixture(7, 16, 6.0, 5101)
+    fv = W.maxwellian_mixture(5, 12, 5.0, 5102)
+    fs = [gpu(fa), gpu(fv)]
+    gs = [gpu(W.cotangent(fa, 5103)), gpu(W.cotangent(fv, 5104))]
+    grp = qc.Group([pa, pv], [7, 5])
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        Qg = grp.eval(fs, conserve=True, use_graph=True, stream=stream)
+        dfe = grp.vjp(fs, gs, through_conserve=True, use_graph=False, stream=stream)
+        dfg = grp.vjp(fs, gs, dfs=[torch.empty_like(x) for x in fs], through_conserve=True, use_graph=True,
+                      stream=stream)
+    torch.cuda.synchronize()
+    for i, p in enumerate((pa, pv)):
+        Q = p.eval(fs[i])
+        p.conserve(Q)
+        df, _ = p.vjp(fs[i], gs[i], through_conserve=True)
+        assert torch.equal(Q, Qg[i])
+        assert torch.equal(df, dfe[i]) and torch.equal(df, dfg[i])
+    grp.close()
