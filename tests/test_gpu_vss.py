@@ -210,3 +210,33 @@ def test_vss_fused_schedule_matches_two_pass(N):
     e2 = rel(two.eval(f).cpu().numpy(), ref)
     print(f"VSS N={N}: fused {e1:.3e} two-pass {e2:.3e}", flush=True)
     assert e1 <= 2e-5 and e2 <= 2e-5
+
+
+@pytest.mark.timeout(600)
+def test_vss_vjp_48_sub_chunks():
+    """VSS VJP at 48^3 with the uneven batch's 48^3 node and sphere counts
+    (N_rho = 24, M = 12), FP32: 31 items run as one chunk of three 10-item
+    sub-chunks (the paired h_pq volumes of each sub-chunk read the spectrum of
+    g, whose first volumes hold the accumulation's second half by then) plus a
+    ragged chunk of one.  Items of each sub-chunk equal per-item calls bit for
+    bit, and three items agree with the FP64 plan within the FP32 VJP bound."""
+    N, L, Nr, M, al = 48, 9.0, 24, 12, 1.5
+    sph = W.sphere_rule(M)
+    print("case vss vjp 48^3, 31 items", flush=True)
+    f = W.maxwellian_mixture(31, N, L, 4800, T_range=(2.5, 3.5))
+    g = W.cotangent(f, 4801)
+    p32 = qc.Plan(N, L, Nr, sphere=sph, omega=0.81, precision=qc.QCOLL_FP32, alpha=al)
+    fb, gb = gpu(f), gpu(g)
+    dfb, dwb = p32.vjp(fb, gb, want_domega=True)
+    for i in (0, 15, 29, 30):
+        d1, w1 = p32.vjp(fb[i:i + 1].contiguous(), gb[i:i + 1].contiguous(), want_domega=True)
+        assert torch.equal(d1[0], dfb[i]) and torch.equal(w1[0], dwb[i]), i
+    p64 = qc.Plan(N, L, Nr, sphere=sph, omega=0.81, precision=qc.QCOLL_FP64, alpha=al)
+    idx = [0, 15, 30]
+    d64, w64 = p64.vjp(fb[idx].contiguous(), gb[idx].contiguous(), want_domega=True)
+    e = rel(dfb[idx].cpu().numpy(), d64.cpu().numpy())
+    ew = float(np.max(np.abs(dwb[idx].cpu().numpy() - w64.cpu().numpy()) / np.abs(w64.cpu().numpy())))
+    print(f"vss vjp 48^3 FP32 vs FP64: df {e:.3e} domega {ew:.3e}", flush=True)
+    assert e <= VJP_TOL[qc.QCOLL_FP32][0] and ew <= VJP_TOL[qc.QCOLL_FP32][1]
+    p32.close()
+    p64.close()
