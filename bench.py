@@ -292,20 +292,29 @@ def stream_probe(mib=1024, reps=20):
     print(json.dumps({"stream_probe_MiB": mib, **out}))
 
 
-def extras(qc, torch, W, reps=3):
+def median_call_ms(torch, fn, n):
+    """Wall time of one call: the median of n synchronised calls after an
+    untimed one (the secondary rows are single calls of 0.3-100 ms, where one
+    slow call would move a mean)."""
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(n):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)) * 1e3
+
+
+def extras(qc, torch, W, reps=7):
     """Secondary measurements of the rows outside the headline step, each on its
     own synthetic workload: the DG weak-form term with the MFMA contractions,
     the VJP, and the group launches.  Wall time per call after one untimed call."""
     out = {}
 
     def timeit(fn, n=reps):
-        fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(n):
-            fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / n * 1e3
+        return median_call_ms(torch, fn, n)
 
     # DG weak form on the 1D DG batch: 64 elements, P = 2 on Gauss nodes (K = 3).
     # Collocation form T = I, W = diag(w_q) (192 Q evals) and eigen form of the
@@ -433,17 +442,11 @@ def extras(qc, torch, W, reps=3):
     return out
 
 
-def group_uneven(qc, torch, W, reps=3):
+def group_uneven(qc, torch, W, reps=7):
     """The uneven three-grid batch through the autotuned group graph (eval with
     the projection, and the VJP through it), and each branch alone."""
     def timeit(fn):
-        fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / reps * 1e3
+        return median_call_ms(torch, fn, reps)
 
     out = {}
     stream = torch.cuda.Stream()
