@@ -269,27 +269,37 @@ def copy_probe(mib=1024, reps=5):
     print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "reps": reps}))
 
 
-def stream_probe(mib=1024, reps=20):
+def stream_probe(mib=1024, reps=20, copy_sizes=(16, 32, 64, 128, 192, 256, 512)):
     """Achievable HBM rates on this device: a 1 GiB copy (read + write), a
-    1 GiB fill (write only) and a 1 GiB sum (read only), timed with events."""
+    1 GiB fill (write only) and a 1 GiB sum (read only), timed with events;
+    then copies of smaller buffers, whose source and destination fit the
+    Infinity Cache (256 MiB) or the L2s (8 x 4 MiB)."""
     import torch
+
+    def rate(fn, nbytes, n_rep):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n_rep):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / n_rep
+        return {"ms": round(ms, 4), "GB_per_s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+
     n = mib * (1 << 20) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     out = {}
     for name, fn, nbytes in (("copy", lambda: b.copy_(a), 8 * n), ("fill", lambda: b.fill_(1.5), 4 * n),
                              ("read", lambda: a.sum(), 4 * n)):
-        for _ in range(3):
-            fn()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        out[name] = {"ms": round(ms, 4), "GB_per_s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
-    print(json.dumps({"stream_probe_MiB": mib, **out}))
+        out[name] = rate(fn, nbytes, reps)
+    copies = {}
+    for m in copy_sizes:
+        k = m * (1 << 20) // 4
+        copies[str(m)] = rate(lambda: b[:k].copy_(a[:k]), 8 * k, max(reps, 2048 // m))["GB_per_s"]
+    print(json.dumps({"stream_probe_MiB": mib, **out, "copy_GB_per_s_by_MiB": copies}))
 
 
 def median_call_ms(torch, fn, n):
