@@ -37,6 +37,9 @@ WORKLOAD = "dg1d_32"
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK = 157.3        # TFLOP/s, published (packed FP32)
 FP32_VALU_NONPACKED = 78.6    # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
+FP64_VALU_PEAK = 78.6         # TFLOP/s, published FP64 vector (one FP64 FMA per lane and clock)
+# on-chip gain kernels (ALU bound): every term's transform and products stay in registers and LDS
+ONCHIP_GAIN = ("gain fused", "gain c2", "gain q64")
 
 
 def _oracle_item(args):
@@ -166,6 +169,9 @@ def algorithmic_bytes(role, fp32, B, N, Nr, M, npair, nv, half=None):
         "sum nodes": B * nh * (8 * Nr + 16),
         "conserve": B * n3 * (8 + 8),
         "gain fused": B * n3 * 8 + B * Nr * nh * 8,
+        # FP64 on chip: the item spectrum once (its Nr classes re-read it from L2), A_p written once
+        "gain c2": B * n3 * 16 + B * Nr * n3 * 8,
+        "gain q64": B * n3 * 16 + B * Nr * n3 * 8,
     }
     return m.get(role)
 
@@ -184,7 +190,7 @@ def hbm_passes(kt, steps, fp32, B, N, Nr, M, npair, nv, half=None):
             gbs = b / (ms_step * 1e-3) / 1e9
             ent.update({"algorithmic_MB": round(b / 1e6, 2), "GB_per_s": round(gbs, 1),
                         "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
-            if role != "gain fused":
+            if role not in ONCHIP_GAIN:
                 tot_b += b
                 tot_ms += ms_step
         out[role] = ent
@@ -244,6 +250,16 @@ def roofline(name, tot_ms, launches, steps, B, N, Nr, M, fp32=True, npair=0, nv=
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_VALU_PEAK, 4),
                      "flops_per_launch": per_launch,
                      "peak_nonpacked_fp32": FP32_VALU_NONPACKED})
+        return base
+    if name in ("gain c2", "gain q64"):
+        # FP64 gain loop on chip: model flops of every (item, p, q) term (the
+        # low-rank stage runs after it as two passes)
+        flops = B * Nr * steps * M * model_flops_per_term(N)
+        per_launch = flops / launches
+        achieved = per_launch / (avg_ms * 1e-3) / 1e12
+        base.update({"bound": "alu", "achieved": round(achieved, 2), "peak": FP64_VALU_PEAK,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP64_VALU_PEAK, 4),
+                     "flops_per_launch": per_launch})
         return base
     b = algorithmic_bytes(name, fp32, B, N, Nr, M, npair, nv)
     total = None if b is None else b * steps

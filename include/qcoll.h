@@ -164,7 +164,7 @@ qcoll_status qcoll_plan_table(qcoll_plan plan, int32_t which, double *host_out, 
 qcoll_status qcoll_plan_set_omega(qcoll_plan plan, double omega);
 
 /* Hot-loop schedule: 0 = automatic (on-chip kernel where it is available:
- * FP32 with N <= 32, FP64 with N = 16; otherwise two passes over HBM),
+ * FP32 with N <= 32, FP64 with N = 16 or 32; otherwise two passes over HBM),
  * 1 = force the two-pass schedule, 2 = require the on-chip kernel (ENOTSUP
  * where it is not available).  Results agree to rounding; workspace sizes depend on it.
  * The schedule requested here also selects the gain adjoint of qcoll_vjp

@@ -210,7 +210,7 @@ qcoll_status qcoll_plan_set_schedule(qcoll_plan plan, int32_t schedule) {
   if (!plan) return fail(QCOLL_EINVAL, "plan is NULL");
   if (schedule < 0 || schedule > 2) return fail(QCOLL_EINVAL, "schedule must be 0, 1 or 2");
   if (schedule == 2 && !qcoll::onchip_schedule_supported(plan->p))
-    return fail(QCOLL_ENOTSUP, "the on-chip gain kernels need FP32 with N <= 32 or FP64 with N = 16, "
+    return fail(QCOLL_ENOTSUP, "the on-chip gain kernels need FP32 with N <= 32 or FP64 with N = 16 or 32, "
                                "and the symmetric Nyquist convention");
   plan->p.schedule = schedule;
   plan->p.schedule_user = schedule;

@@ -22,6 +22,11 @@ __device__ __forceinline__ cplx<float> load_c32(__amdgpu_buffer_rsrc_t r, int vo
   return cplx<float>{v.x, v.y};
 }
 
+__device__ __forceinline__ cplx<double> load_c64(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  const double2 v = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  return cplx<double>{v.x, v.y};
+}
+
 template <int N>
 struct FusedGeom {
   // pencils per lane (1: N^2 lanes; the loops below also support 2, which

@@ -24,9 +24,10 @@
 //
 // The kernel is written for any N divisible by 4, but it is launched only at
 // N = 16 (1.4x faster than the two-pass schedule there).  From N = 24 a lane's
-// pencil, its FFT temporaries and the N-double accumulator exceed 256 VGPRs;
-// at one wave per SIMD the per-term reloads of the item spectrum from L2 are
-// not hidden and the two-pass schedule is faster (2x at 24^3, 1.3x at 32^3).
+// four pencils, their FFT temporaries and the N-double accumulator exceed 256
+// VGPRs; at one wave per SIMD the per-term reloads of the item spectrum from L2
+// are not hidden.  At N = 32 the kernel below splits j1 in two classes
+// instead: one pencil per lane, two waves per SIMD.
 #include <hip/hip_runtime.h>
 
 #include "qcoll_fused.hpp"
@@ -189,6 +190,178 @@ __global__ __launch_bounds__(Q64Geom<N>::NL, 2) void k_gain_q64(const cplx<doubl
   static_for<0, N>([&](auto j) { a[decltype(j)::value * n2] = acc[decltype(j)::value]; });
 }
 
+// FP64 gain loop on chip at N = 32, two residue classes of the first output
+// index (j1 = 2v + g, v < N/2): a workgroup of N^2/2 lanes (two waves per
+// SIMD) runs the same sum for one (item, node) pair and one class, whose
+// volume (N/2 x N x N complex doubles) is one N-point pencil per lane.  With
+// k1 = (N/2) a + b,
+//   u(2v + g) = sum_b e^(2 pi i b v / (N/2)) [e^(2 pi i g b / N) (X(b) + (-1)^g X(N/2 + b))].
+//   stage A  lane l holds two pencils (k2, k3) = (l / N + (N/2) m, l % N),
+//            m < 2, loaded along k1 with the shift multiplier applied
+//            (consecutive lanes read consecutive k3), folded and transformed
+//            (N/2 points): v = 0..N/2-1 each;
+//   stage B  lane (v, k3) after a transpose across the workgroup: axis 2;
+//   stage C  lane (v, j2) after a transpose inside the wave (a wave holds
+//            whole planes v): axis 3, then the product; the lane owns
+//            A_p[2v + g][j2][:] across all q.
+// One component at a time through a tile of N/2 x N x (N+1) doubles (135 KiB);
+// the odd row stride keeps the strided reads free of bank conflicts.
+template <int N>
+struct C2Geom {
+  static constexpr int NV = N / 2;
+  static constexpr int NL = N * N / 2;
+  static constexpr int R = N + 1;
+  static constexpr int S = N * R;
+  static constexpr size_t lds_bytes = size_t(NV) * S * sizeof(double);
+  static constexpr bool WAVE_BC = (64 % N == 0);
+};
+
+template <int N, int G>
+__device__ __forceinline__ void c2_stage_a(__amdgpu_buffer_rsrc_t hr, const cplx<double> *__restrict__ ph,
+                                           int lane, double sc, double *zr, double *zi) {
+  constexpr int NV = C2Geom<N>::NV, NL = C2Geom<N>::NL;
+  constexpr long n2 = long(N) * N;
+  static_for<0, 2>([&](auto mm) {
+    constexpr int m = decltype(mm)::value;
+    const int t = lane + m * NL;   // pencil (k2, k3) = (t / N, t % N)
+    const cplx<double> b2 = ph[N + t / N], b3 = ph[2 * N + t % N];
+    // c_s(k1) = Re(b1 b2 b3) + Im(b1 b2 b3) = b1.re P + b1.im Qm, times 1/N^3 sqrt(w_q)
+    const double xr = b2.re * b3.re - b2.im * b3.im;
+    const double yi = b2.re * b3.im + b2.im * b3.re;
+    const double P = (xr + yi) * sc, Qm = (xr - yi) * sc;
+    static_for<0, NV>([&](auto bb) {
+      constexpr int b = decltype(bb)::value;
+      // buffer loads with the element offset as a scalar: no per-element
+      // address registers to keep across the term loop
+      const int vo = int(t * sizeof(cplx<double>));
+      const cplx<double> h0 = load_c64(hr, vo, int(b * n2 * sizeof(cplx<double>)));
+      const cplx<double> h1 = load_c64(hr, vo, int((NV + b) * n2 * sizeof(cplx<double>)));
+      const cplx<double> e0 = ph[b], e1 = ph[NV + b];
+      const double c0 = e0.re * P + e0.im * Qm, c1 = e1.re * P + e1.im * Qm;
+      double yr, yim;
+      if constexpr (G == 0) {
+        yr = h0.re * c0 + h1.re * c1;
+        yim = h0.im * c0 + h1.im * c1;
+      } else {
+        yr = h0.re * c0 - h1.re * c1;
+        yim = h0.im * c0 - h1.im * c1;
+      }
+      twiddle<N, G * b, +1, double>(yr, yim);   // e^(2 pi i G b / N)
+      zr[m * NV + b] = yr;
+      zi[m * NV + b] = yim;
+    });
+    fft_reg<NV, +1, double>(zr + m * NV, zi + m * NV);
+  });
+}
+
+template <int N>
+__global__ __launch_bounds__(C2Geom<N>::NL) void k_gain_c2(const cplx<double> *__restrict__ H,
+                                                          const cplx<double> *__restrict__ phase,
+                                                          const double *__restrict__ wq, double *__restrict__ A,
+                                                          long nbp, int M, int Nr, double scale) {
+  using Gm = C2Geom<N>;
+  constexpr int NV = Gm::NV, R = Gm::R, S = Gm::S;
+  constexpr long n2 = long(N) * N, n3 = n2 * N;
+  extern __shared__ double tile[];
+
+  const long lb = xcd_block();
+  if (lb >= nbp * 2) return;  // uniform per workgroup
+  const long bp = lb / 2;
+  const int g = int(lb % 2);
+  const long b = bp / Nr;
+  const int p = int(bp % Nr);
+  const int lane = threadIdx.x;
+  const int k2a = lane / N, k3a = lane % N;   // stage A: pencils (k2a + NV m, k3a)
+  const int vb = lane / N, cb = lane % N;     // stages B and C: v, and k3 (B) or j2 (C)
+
+  double acc[N];
+  static_for<0, N>([&](auto j) { acc[decltype(j)::value] = 0.0; });
+  const __amdgpu_buffer_rsrc_t hr = make_rsrc(H + b * n3, unsigned(n3 * sizeof(cplx<double>)));
+  for (int q = 0; q < M; ++q) {
+    const cplx<double> *ph = phase + size_t(p * M + q) * 3 * N;
+    const double sc = scale * __builtin_sqrt(wq[q]);
+    double zr[N], zi[N];
+    if (g == 0) c2_stage_a<N, 0>(hr, ph, lane, sc, zr, zi);
+    else c2_stage_a<N, 1>(hr, ph, lane, sc, zr, zi);
+    // A -> B (across waves): element (v, k2, k3) at v*S + k2*R + k3.  The
+    // previous term's stage-C reads stay inside each wave's own planes, so one
+    // barrier before the writes orders them against other waves' reads.
+    __syncthreads();
+    auto a_to_b = [&](double *z, bool tail) {
+      static_for<0, 2>([&](auto mm) {
+        constexpr int m = decltype(mm)::value;
+        static_for<0, NV>([&](auto vv) {
+          constexpr int v = decltype(vv)::value;
+          tile[v * S + (k2a + NV * m) * R + k3a] = z[m * NV + v];
+        });
+      });
+      __syncthreads();
+      static_for<0, N>([&](auto kk) { z[decltype(kk)::value] = tile[vb * S + decltype(kk)::value * R + cb]; });
+      if (tail) __syncthreads();
+    };
+    a_to_b(zr, true);
+    a_to_b(zi, false);
+    fft_reg<N, +1, double>(zr, zi);   // axis 2: lane (v, k3) now holds j2 = 0..N-1
+    // B -> C: element (v, j2, k3) at v*S + j2*R + k3; plane v belongs to the
+    // N lanes of one wave (64 % N == 0), so the wave orders its own accesses.
+    // Before the first write every wave must be done reading the A -> B tile.
+    __syncthreads();
+    auto b_to_c = [&](double *z) {
+      static_for<0, N>([&](auto jj) { tile[vb * S + decltype(jj)::value * R + cb] = z[decltype(jj)::value]; });
+      if constexpr (Gm::WAVE_BC) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      } else {
+        __syncthreads();
+      }
+      static_for<0, N>([&](auto kk) { z[decltype(kk)::value] = tile[vb * S + cb * R + decltype(kk)::value]; });
+      if constexpr (Gm::WAVE_BC) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      } else {
+        __syncthreads();
+      }
+    };
+    b_to_c(zr);
+    b_to_c(zi);
+    fft_reg<N, +1, double>(zr, zi);   // axis 3: lane (v, j2) holds j3 = 0..N-1
+    static_for<0, N>([&](auto j) {
+      constexpr int jj = decltype(j)::value;
+      acc[jj] += zr[jj] * zr[jj];
+      acc[jj] -= zi[jj] * zi[jj];
+    });
+  }
+  // A_p[2v + g][j2][j3]: N consecutive doubles per lane
+  double2 *a = reinterpret_cast<double2 *>(A + bp * n3 + long(2 * vb + g) * n2 + long(cb) * N);
+  static_for<0, N / 2>([&](auto j) {
+    constexpr int jj = decltype(j)::value;
+    a[jj] = make_double2(acc[2 * jj], acc[2 * jj + 1]);
+  });
+}
+
+template <int N>
+static qcoll_status launch_c2(const Plan &p, const cplx<double> *H, double *A, long nbp, hipStream_t st) {
+  using G = C2Geom<N>;
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_gain_c2<N>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, int(G::lds_bytes)) != hipSuccess) {
+    set_error("hipFuncSetAttribute failed for the FP64 gain kernel");
+    return QCOLL_EDEVICE;
+  }
+  TimedLaunch tl("gain c2", st);
+  const double scale = 1.0 / double(long(N) * N * N);
+  hipLaunchKernelGGL((k_gain_c2<N>), dim3(unsigned(nbp * 2)), dim3(G::NL), G::lds_bytes, st, H,
+                     reinterpret_cast<const cplx<double> *>(p.phase), reinterpret_cast<const double *>(p.wq), A,
+                     nbp, p.M, p.N_rho, scale);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error(std::string("gain c2: ") + hipGetErrorString(e));
+    return QCOLL_EDEVICE;
+  }
+  return QCOLL_OK;
+}
+
 template <int N>
 static qcoll_status launch_q64(const Plan &p, const cplx<double> *H, double *A, long nbp, hipStream_t st) {
   using G = Q64Geom<N>;
@@ -210,7 +383,7 @@ static qcoll_status launch_q64(const Plan &p, const cplx<double> *H, double *A, 
   return QCOLL_OK;
 }
 
-bool gain_q64_supported(int N, int precision) { return precision == QCOLL_FP64 && N == 16; }
+bool gain_q64_supported(int N, int precision) { return precision == QCOLL_FP64 && (N == 16 || N == 32); }
 
 bool use_gain_q64(const Plan &p) {
   return p.schedule != 1 && !p.is_vss() && !p.literal && gain_q64_supported(p.N, p.precision);
@@ -220,6 +393,7 @@ qcoll_status launch_gain_q64(const Plan &p, const void *H, double *A, long nbp, 
   const auto *h = static_cast<const cplx<double> *>(H);
   switch (p.N) {
     case 16: return launch_q64<16>(p, h, A, nbp, st);
+    case 32: return launch_c2<32>(p, h, A, nbp, st);
     default: set_error("FP64 on-chip gain kernel: unsupported N"); return QCOLL_ENOTSUP;
   }
 }

@@ -226,10 +226,11 @@ def test_schedule_requests_are_validated():
         plan64.set_schedule(2)
     with pytest.raises(qc.QcollError):
         plan64.set_schedule(5)
-    # FP64 on-chip gain kernel: N = 16 only
+    # FP64 on-chip gain kernels: N = 16 (four classes of j2) and N = 32 (two classes of j1)
     qc.Plan(16, 6.0, 2, sphere=None, omega=0.81, precision=qc.QCOLL_FP64).set_schedule(2)
+    qc.Plan(32, 6.0, 2, sphere=None, omega=0.81, precision=qc.QCOLL_FP64).set_schedule(2)
     with pytest.raises(qc.QcollError):
-        qc.Plan(32, 6.0, 2, sphere=None, omega=0.81, precision=qc.QCOLL_FP64).set_schedule(2)
+        qc.Plan(24, 6.0, 2, sphere=None, omega=0.81, precision=qc.QCOLL_FP64).set_schedule(2)
 
 
 def test_fp64_onchip_gain_matches_oracle_and_two_pass():
@@ -259,3 +260,36 @@ def test_fp64_onchip_gain_matches_oracle_and_two_pass():
     e = rel_linf(onchip.eval(fb).cpu().numpy(), two.eval(fb).cpu().numpy())
     print(f"70 items: on-chip vs two-pass {e:.3e}", flush=True)
     assert e <= 1e-13
+
+
+def test_fp64_onchip_gain_32_matches_oracle_and_two_pass():
+    """FP64 plans at N = 32 run the gain loop on chip over the two residue
+    classes of j1 (one workgroup per (item, node) pair and class, a 16-point
+    transform after the two-term combination along axis 1): three items
+    against the oracle; 35 items in three chunks (ragged tail) against the
+    two-pass schedule; and each item's result independent of the chunking."""
+    N, L, N_rho, M = 32, 6.0, 4, 12
+    print("case fp64 on-chip gain N=32", flush=True)
+    sph = W.sphere_rule(M)
+    P = spectral.Params(N, L, N_rho, sph[0], sph[1], 0.81)
+    onchip = qc.Plan(N, L, N_rho, sphere=sph, omega=0.81, precision=qc.QCOLL_FP64)
+    onchip.set_schedule(2)
+    two = qc.Plan(N, L, N_rho, sphere=sph, omega=0.81, precision=qc.QCOLL_FP64)
+    two.set_schedule(1)
+    f = W.maxwellian_mixture(3, N, L, 618, noise=0.05)
+    ref = spectral.collide_batch(f, P)
+    fg = gpu(f)
+    Q1 = onchip.eval(fg).cpu().numpy()
+    Q2 = two.eval(fg).cpu().numpy()
+    e1, e2, e12 = rel_linf(Q1, ref), rel_linf(Q2, ref), rel_linf(Q1, Q2)
+    print(f"on-chip {e1:.3e} two-pass {e2:.3e} between {e12:.3e}", flush=True)
+    assert e1 <= 1e-12 and e2 <= 1e-12 and e12 <= 1e-13
+    assert onchip.workspace_bytes(3) < two.workspace_bytes(3)
+    fb = gpu(W.maxwellian_mixture(35, N, L, 619, noise=0.05))
+    onchip.set_chunk(16)
+    Qc = onchip.eval(fb)
+    e = rel_linf(Qc.cpu().numpy(), two.eval(fb).cpu().numpy())
+    print(f"35 items: on-chip vs two-pass {e:.3e}", flush=True)
+    assert e <= 1e-13
+    onchip.set_chunk(35)
+    assert torch.equal(Qc, onchip.eval(fb))
