@@ -214,6 +214,11 @@ struct C2Geom {
   static constexpr int S = N * R;
   static constexpr size_t lds_bytes = size_t(NV) * S * sizeof(double);
   static constexpr bool WAVE_BC = (64 % N == 0);
+  // stage-A outputs whose two loads each are issued together: eight loads in
+  // flight (four outputs) fit beside the accumulator and the outputs; with
+  // the loads of one output at a time (waits after every pair) the kernel ran
+  // 12% slower, with eight outputs per group it spills 32 registers
+  static constexpr int KG = 4;
 };
 
 template <int N, int G>
@@ -229,13 +234,23 @@ __device__ __forceinline__ void c2_stage_a(__amdgpu_buffer_rsrc_t hr, const cplx
     const double xr = b2.re * b3.re - b2.im * b3.im;
     const double yi = b2.re * b3.im + b2.im * b3.re;
     const double P = (xr + yi) * sc, Qm = (xr - yi) * sc;
-    static_for<0, NV>([&](auto bb) {
-      constexpr int b = decltype(bb)::value;
-      // buffer loads with the element offset as a scalar: no per-element
-      // address registers to keep across the term loop
-      const int vo = int(t * sizeof(cplx<double>));
-      const cplx<double> h0 = load_c64(hr, vo, int(b * n2 * sizeof(cplx<double>)));
-      const cplx<double> h1 = load_c64(hr, vo, int((NV + b) * n2 * sizeof(cplx<double>)));
+    // buffer loads with the element offset as a scalar: no per-element
+    // address registers to keep across the term loop.  The loads of KG
+    // outputs are issued together (2 KG in flight) before their arithmetic.
+    const int vo = int(t * sizeof(cplx<double>));
+    constexpr int KG = C2Geom<N>::KG;
+    static_for<0, NV / KG>([&](auto gg) {
+      constexpr int g0 = decltype(gg)::value * KG;
+      cplx<double> hl[KG], hh[KG];
+      static_for<0, KG>([&](auto ii) {
+        constexpr int b = g0 + decltype(ii)::value;
+        hl[decltype(ii)::value] = load_c64(hr, vo, int(b * n2 * sizeof(cplx<double>)));
+        hh[decltype(ii)::value] = load_c64(hr, vo, int((NV + b) * n2 * sizeof(cplx<double>)));
+      });
+      __builtin_amdgcn_sched_barrier(0);
+      static_for<0, KG>([&](auto ii) {
+      constexpr int b = g0 + decltype(ii)::value;
+      const cplx<double> h0 = hl[decltype(ii)::value], h1 = hh[decltype(ii)::value];
       const cplx<double> e0 = ph[b], e1 = ph[NV + b];
       const double c0 = e0.re * P + e0.im * Qm, c1 = e1.re * P + e1.im * Qm;
       double yr, yim;
@@ -249,6 +264,8 @@ __device__ __forceinline__ void c2_stage_a(__amdgpu_buffer_rsrc_t hr, const cplx
       twiddle<N, G * b, +1, double>(yr, yim);   // e^(2 pi i G b / N)
       zr[m * NV + b] = yr;
       zi[m * NV + b] = yim;
+      });
+      __builtin_amdgcn_sched_barrier(0);
     });
     fft_reg<NV, +1, double>(zr + m * NV, zi + m * NV);
   });
