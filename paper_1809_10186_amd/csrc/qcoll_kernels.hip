@@ -197,16 +197,26 @@ template <typename T, int N, typename U = T>
 struct SrcPair {
   const T *B;
   int S, npair;
+  static constexpr bool kGroupedLoads = true;
   __device__ C<U> operator()(long g, int r, int c) const {
+    const C<T> v = raw(g, r, c);
+    return C<U>{U(v.re), U(v.im)};
+  }
+  __device__ C<T> raw(long g, int r, int c) const {
     constexpr long n3 = long(N) * N * N;
     const long t = g / N;
     const int j1 = int(g % N);
     const long b = t / npair;
     const int s = int(t % npair);
     const long o = (long(j1) * N + r) * N + c;
+    // the odd row of the last pair may be missing (S odd): load the even row
+    // again and select zero, so that every load is unconditional (a branch
+    // per element would make each load wait for the previous one)
+    const bool has_im = 2 * s + 1 < S;
     const T re = B[(b * S + 2 * s) * n3 + o];
-    const T im = (2 * s + 1 < S) ? B[(b * S + 2 * s + 1) * n3 + o] : T(0);
-    return C<U>{U(re), U(im)};
+    const T im_raw = B[(b * S + 2 * s + (has_im ? 1 : 0)) * n3 + o];
+    const T im = has_im ? im_raw : T(0);
+    return C<T>{re, im};
   }
 };
 
@@ -238,12 +248,34 @@ struct OpLowRank {
       fft_reg<N, -1, T>(xr, xi);
       const T *v0 = V + (2 * s) * n3 + r;
       const T *v1 = V + (2 * s + 1) * n3 + r;
-      static_for<0, N>([&](auto k) {
-        constexpr int kk = decltype(k)::value;
-        const T a = v0[kk * n2], c = v1[kk * n2];
-        // (a - i c)(xr + i xi) = (a xr + c xi) + i (a xi - c xr)
-        tr[kk] += a * xr[kk] + c * xi[kk];
-        ti[kk] += a * xi[kk] - c * xr[kk];
+      // the V rows in groups of KV values, each group's loads issued together
+      // before its products (otherwise every pair of loads is waited for
+      // alone); at N = 64 the accumulator and the pencil already fill the
+      // register file, and the groups only add spills
+      constexpr int KV = (N >= 64) ? N : ((N % 8 == 0) ? 8 : ((N % 6 == 0) ? 6 : 4));
+      if constexpr (KV == N) {
+        static_for<0, N>([&](auto k) {
+          constexpr int kk = decltype(k)::value;
+          const T a = v0[kk * n2], c = v1[kk * n2];
+          tr[kk] += a * xr[kk] + c * xi[kk];
+          ti[kk] += a * xi[kk] - c * xr[kk];
+        });
+      } else
+      static_for<0, N / KV>([&](auto gg) {
+        constexpr int k0 = decltype(gg)::value * KV;
+        T av[KV], cv[KV];
+        static_for<0, KV>([&](auto ii) {
+          av[decltype(ii)::value] = v0[(k0 + decltype(ii)::value) * n2];
+          cv[decltype(ii)::value] = v1[(k0 + decltype(ii)::value) * n2];
+        });
+        __builtin_amdgcn_sched_barrier(0);
+        static_for<0, KV>([&](auto ii) {
+          constexpr int kk = k0 + decltype(ii)::value;
+          const T a = av[decltype(ii)::value], c = cv[decltype(ii)::value];
+          // (a - i c)(xr + i xi) = (a xr + c xi) + i (a xi - c xr)
+          tr[kk] += a * xr[kk] + c * xi[kk];
+          ti[kk] += a * xi[kk] - c * xr[kk];
+        });
       });
     }
     C<double> *o = TA + b * n3 + r;

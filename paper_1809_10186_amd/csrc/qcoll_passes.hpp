@@ -73,6 +73,15 @@ constexpr int slab_spb() {
   return slab_split<T, N>() ? spb_for(N, N * (N + 1) * int(sizeof(T))) : slab_spb2<T, N>();
 }
 
+// Sources that declare kGroupedLoads provide raw(g, r, c), the element in its
+// stored precision; k_slab then issues the loads of a group of rows together
+// and widens them afterwards (left to itself, the compiler reuses a few
+// registers for the raw values and waits for every load on its own).
+template <class S, class = void>
+struct grouped_loads : std::false_type {};
+template <class S>
+struct grouped_loads<S, std::void_t<decltype(S::kGroupedLoads)>> : std::bool_constant<S::kGroupedLoads> {};
+
 // Generic slab kernel: Src(g, r, c) -> C<T> loads element (r, c) of slab g with
 // any prologue; Dst(g, r, c, v) stores.  Slabs g >= nslab are skipped.
 //
@@ -91,11 +100,25 @@ __global__ __launch_bounds__(256) void k_slab(Src src, Dst dst, long nslab) {
   const long g = long(blockIdx.x) * SPB + s;
   const long gl = g < nslab ? g : nslab - 1;
   T xr[N], xi[N];
-  static_for<0, N>([&](auto r) {
-    const C<T> v = src(gl, decltype(r)::value, c);
-    xr[decltype(r)::value] = v.re;
-    xi[decltype(r)::value] = v.im;
-  });
+  if constexpr (grouped_loads<Src>::value) {
+    constexpr int LG = (N % 16 == 0) ? 16 : ((N % 8 == 0) ? 8 : 4);
+    static_for<0, N / LG>([&](auto gg) {
+      constexpr int r0 = decltype(gg)::value * LG;
+      decltype(src.raw(gl, 0, c)) v[LG];
+      static_for<0, LG>([&](auto ii) { v[decltype(ii)::value] = src.raw(gl, r0 + decltype(ii)::value, c); });
+      __builtin_amdgcn_sched_barrier(0);
+      static_for<0, LG>([&](auto ii) {
+        xr[r0 + decltype(ii)::value] = T(v[decltype(ii)::value].re);
+        xi[r0 + decltype(ii)::value] = T(v[decltype(ii)::value].im);
+      });
+    });
+  } else {
+    static_for<0, N>([&](auto r) {
+      const C<T> v = src(gl, decltype(r)::value, c);
+      xr[decltype(r)::value] = v.re;
+      xi[decltype(r)::value] = v.im;
+    });
+  }
   fft_reg<N, SIGN, T>(xr, xi);
   if constexpr (SPLIT) {
     // one tile, one component at a time: column -> row, row FFT, row -> column
