@@ -94,15 +94,38 @@ __global__ __launch_bounds__(FusedGeom<N>::NL, FusedGeom<N>::WPE) void k_gain_fu
       const float xr = b2.re * b3.re - b2.im * b3.im;
       const float yi = b2.re * b3.im + b2.im * b3.re;
       const float P = (xr + yi) * sc, Qm = (xr - yi) * sc;
-      static_for<0, N>([&](auto k) {
-        constexpr int kk = decltype(k)::value;
-        const cplx<float> v = load_c32(hr, int((lane + u * NL) * sizeof(cplx<float>)),
-                                       int(kk * n2 * sizeof(cplx<float>)));
-        const cplx<float> b1 = ph[kk];
-        const float c = b1.re * P + b1.im * Qm;
-        zr[u][kk] = v.re * c;
-        zi[u][kk] = v.im * c;
-      });
+      if constexpr (VSS && N == 32) {
+        // VSS mode holds its half-spectrum sum besides the pencil: the loads
+        // go in groups of eight, each group's loads issued before its
+        // products (left to itself the compiler waits for the later loads one
+        // by one)
+        static_for<0, N / 8>([&](auto gg) {
+          constexpr int k0 = decltype(gg)::value * 8;
+          cplx<float> v[8];
+          static_for<0, 8>([&](auto ii) {
+            v[decltype(ii)::value] = load_c32(hr, int((lane + u * NL) * sizeof(cplx<float>)),
+                                              int((k0 + decltype(ii)::value) * n2 * sizeof(cplx<float>)));
+          });
+          __builtin_amdgcn_sched_barrier(0);
+          static_for<0, 8>([&](auto ii) {
+            constexpr int kk = k0 + decltype(ii)::value;
+            const cplx<float> b1 = ph[kk];
+            const float c = b1.re * P + b1.im * Qm;
+            zr[u][kk] = v[decltype(ii)::value].re * c;
+            zi[u][kk] = v[decltype(ii)::value].im * c;
+          });
+        });
+      } else {
+        static_for<0, N>([&](auto k) {
+          constexpr int kk = decltype(k)::value;
+          const cplx<float> v = load_c32(hr, int((lane + u * NL) * sizeof(cplx<float>)),
+                                         int(kk * n2 * sizeof(cplx<float>)));
+          const cplx<float> b1 = ph[kk];
+          const float c = b1.re * P + b1.im * Qm;
+          zr[u][kk] = v.re * c;
+          zi[u][kk] = v.im * c;
+        });
+      }
       fft_reg<N, +1, float>(zr[u], zi[u]);
     });
     // A -> B: element (j1, k2, k3) at j1*S1 + k2*N + k3.  The previous
@@ -177,12 +200,15 @@ __global__ __launch_bounds__(FusedGeom<N>::NL, FusedGeom<N>::WPE) void k_gain_fu
       const float *a = apq + size_t(p * M + q) * (size_t(H1) * n2);
       static_for<0, PPL>([&](auto uu) {
         constexpr int u = decltype(uu)::value;
+        // the term's weights are loaded before the transform, which hides
+        // their latency (loaded after it, each load was waited for alone)
+        float wv[H1];
+        static_for<0, H1>([&](auto k) { wv[decltype(k)::value] = a[decltype(k)::value * n2 + lane + u * NL]; });
         fft_reg<N, -1, float>(zr[u], zi[u]);
         static_for<0, H1>([&](auto k) {
           constexpr int kk = decltype(k)::value;
-          const float w = a[kk * n2 + lane + u * NL];
-          acc[u][2 * kk] += w * zr[u][kk];
-          acc[u][2 * kk + 1] += w * zi[u][kk];
+          acc[u][2 * kk] += wv[kk] * zr[u][kk];
+          acc[u][2 * kk + 1] += wv[kk] * zi[u][kk];
         });
       });
     }
