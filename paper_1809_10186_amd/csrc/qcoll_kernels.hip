@@ -604,6 +604,14 @@ __global__ __launch_bounds__(256) void k_vss_acc(const C<T> *Y, const T *apq, C<
       xr[decltype(r)::value] = v.re;
       xi[decltype(r)::value] = v.im;
     });
+    // the term's weights for this column, loaded before the two transforms
+    // hide their latency (loaded where they are used, each was waited for
+    // alone); not where the extra registers cost occupancy or spill (FP64
+    // at N = 24 and 48)
+    constexpr bool PRE = (sizeof(T) == 4) ? (N <= 48) : (N == 32);
+    const T *a = apq + (size_t(p) * M + q) * nh + long(k1) * n2 + c;
+    T wv[PRE ? N : 1];
+    if constexpr (PRE) static_for<0, N>([&](auto r) { wv[decltype(r)::value] = a[decltype(r)::value * N]; });
     fft_reg<N, -1, T>(xr, xi);
     static_for<0, N>([&](auto r) {
       sre[s][decltype(r)::value][c] = xr[decltype(r)::value];
@@ -621,10 +629,11 @@ __global__ __launch_bounds__(256) void k_vss_acc(const C<T> *Y, const T *apq, C<
       sim[s][row][decltype(k)::value] = xi[decltype(k)::value];
     });
     __syncthreads();
-    const T *a = apq + (size_t(p) * M + q) * nh + long(k1) * n2 + c;
     static_for<0, N>([&](auto r) {
       constexpr int rr = decltype(r)::value;
-      const T w = a[rr * N];
+      T w;
+      if constexpr (PRE) w = wv[rr];
+      else w = a[rr * N];
       ar[rr] += w * sre[s][rr][c];
       ai[rr] += w * sim[s][rr][c];
     });
