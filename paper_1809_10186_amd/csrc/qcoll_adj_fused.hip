@@ -142,6 +142,28 @@ __global__ __launch_bounds__(FusedGeom<N>::NL) void k_adj_fused(const cplx<float
     const float Pm = xr + yi, Qm = xr - yi;
     const float Ps = Pm * scale, Qs = Qm * scale;   // the inverse's 1/N^3, once per term
     const cplx<float> *b1q = b1s + q * N;
+    if constexpr (N == 32) {
+      // the spectrum's loads in groups of eight, each group issued before its
+      // products: left to itself the compiler waits for the later loads one
+      // by one (the adjoint's register budget is full); at 24^3 the groups
+      // made the adjoint slower
+      static_for<0, N / 8>([&](auto gg) {
+        constexpr int k0 = decltype(gg)::value * 8;
+        cplx<float> v[8];
+        static_for<0, 8>([&](auto ii) {
+          v[decltype(ii)::value] = load_c32(hr, int(lane * sizeof(cplx<float>)),
+                                            int((k0 + decltype(ii)::value) * n2 * sizeof(cplx<float>)));
+        });
+        __builtin_amdgcn_sched_barrier(0);
+        static_for<0, 8>([&](auto ii) {
+          constexpr int kk = k0 + decltype(ii)::value;
+          const cplx<float> b1 = b1q[kk];
+          const float c = b1.re * Ps + b1.im * Qs;
+          zr[0][kk] = v[decltype(ii)::value].re * c;
+          zi[0][kk] = v[decltype(ii)::value].im * c;
+        });
+      });
+    } else
     static_for<0, N>([&](auto k) {
       constexpr int kk = decltype(k)::value;
       const cplx<float> v = load_c32(hr, int(lane * sizeof(cplx<float>)), int(kk * n2 * sizeof(cplx<float>)));
