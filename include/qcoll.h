@@ -297,8 +297,9 @@ qcoll_status qcoll_plan_set_chunk(qcoll_plan plan, int32_t items);
  * fastest in the plan and returns it in
  * *host_schedule, *host_chunk (either may be NULL).  Synchronous.  If the
  * environment variable QCOLL_AUTOTUNE_CACHE names a file, choices are read
- * from and appended to it, keyed by (arch, N, N_rho, M, precision, rank,
- * batch rounded up to a power of two). */
+ * from and appended to it, keyed by (arch, the library's schedule set, N,
+ * N_rho, M, precision, rank, batch rounded up to a power of two); entries of
+ * an older schedule set are timed again. */
 size_t qcoll_autotune_workspace_bytes(qcoll_plan plan, int64_t batch);
 qcoll_status qcoll_autotune(qcoll_plan plan, int64_t batch, const double *f, double *Q, void *ws,
                             size_t ws_bytes, void *stream, int32_t *host_schedule, int32_t *host_chunk);

@@ -291,12 +291,18 @@ size_t qcoll_autotune_workspace_bytes(qcoll_plan plan, int64_t batch) {
   return mx;
 }
 
+// Cache entries carry the schedule set they were timed against ("s2": the FP32
+// fused kernels, the FP64 on-chip kernels at 16^3 and 32^3); a build that adds
+// or changes a schedule bumps it, so that an older entry is timed again
+// instead of pinning a plan to what used to be the faster schedule.
+constexpr int kTuneScheduleSet = 2;
+
 static std::string tune_key(const qcoll::Plan &p, int64_t batch) {
   int bucket = 1;
   while (bucket < batch && bucket < (1 << 20)) bucket <<= 1;
   std::ostringstream k;
-  k << "gfx950 N=" << p.N << " Nr=" << p.N_rho << " M=" << p.M << " prec=" << p.precision << " rank=" << p.rank
-    << " batch<=" << bucket;
+  k << "gfx950 s" << kTuneScheduleSet << " N=" << p.N << " Nr=" << p.N_rho << " M=" << p.M
+    << " prec=" << p.precision << " rank=" << p.rank << " batch<=" << bucket;
   return k.str();
 }
 

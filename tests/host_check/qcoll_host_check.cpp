@@ -170,11 +170,11 @@ static void check_autotune_cache(const char *path) {
     EXPECT(false);
     return;
   }
-  std::fprintf(fp, "\n|\n||||\ngfx950 N=8|\ngfx950 N=8 Nr=4 M=6 prec=1 rank=4 batch<=4|x y\n");
-  std::fprintf(fp, "gfx950 N=8 Nr=4 M=6 prec=1 rank=4 batch<=4|999999999999999999999 3\n");
+  std::fprintf(fp, "\n|\n||||\ngfx950 s2 N=8|\ngfx950 s2 N=8 Nr=4 M=6 prec=1 rank=4 batch<=4|x y\n");
+  std::fprintf(fp, "gfx950 s2 N=8 Nr=4 M=6 prec=1 rank=4 batch<=4|999999999999999999999 3\n");
   std::string longline(100000, 'z');
   std::fprintf(fp, "%s|1 2\n", longline.c_str());
-  std::fprintf(fp, "gfx950 N=8 Nr=4 M=6 prec=1 rank=4 batch<=4|1 3 0.1\n");
+  std::fprintf(fp, "gfx950 s2 N=8 Nr=4 M=6 prec=1 rank=4 batch<=4|1 3 0.1\n");
   std::fclose(fp);
   setenv("QCOLL_AUTOTUNE_CACHE", path, 1);
   const int64_t batch = 3;
