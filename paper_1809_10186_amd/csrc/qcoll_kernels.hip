@@ -1051,10 +1051,13 @@ struct Engine {
 // to 32^3: at most 16 pairs per lane) a lane keeps its PPT pairs in registers
 // between the sums and the correction, so Q is read once; PPT = 0 reads it
 // twice.  Both visit a lane's pairs in the same order: the results are
-// bit-identical.
-template <int PPT>
-__global__ __launch_bounds__(1024) void k_conserve(double *Q, double *mom, const double *ginv, int N, double L,
+// bit-identical.  NC > 0 fixes N at compile time, so that rebuilding a point's
+// indices takes shifts and multiplications instead of integer divisions by a
+// runtime value (which dominated the kernel's instruction count).
+template <int PPT, int NC = 0>
+__global__ __launch_bounds__(1024) void k_conserve(double *Q, double *mom, const double *ginv, int Nrt, double L,
                                                    int *flag, double dc3, const double *isc, int K) {
+  const int N = NC > 0 ? NC : Nrt;
   const long n3 = long(N) * N * N;
   const long b = blockIdx.x;
   double2 *q = reinterpret_cast<double2 *>(Q + b * n3);
@@ -1341,11 +1344,13 @@ qcoll_status launch_conserve(const Plan &p, int64_t batch, double *Q, double *mo
                        dc * dc * dc, isc, K);
   };
   switch (p.N) {
-    case 8:
-    case 12: go(k_conserve<1>); break;
-    case 16: go(k_conserve<2>); break;
-    case 24: go(k_conserve<7>); break;
-    case 32: go(k_conserve<16>); break;
+    case 8: go(k_conserve<1, 8>); break;
+    case 12: go(k_conserve<1, 12>); break;
+    case 16: go(k_conserve<2, 16>); break;
+    case 24: go(k_conserve<7, 24>); break;
+    case 32: go(k_conserve<16, 32>); break;
+    case 48: go(k_conserve<0, 48>); break;
+    case 64: go(k_conserve<0, 64>); break;
     default: go(k_conserve<0>); break;
   }
   QC_LAUNCH_CHECK("conserve");
