@@ -1130,9 +1130,14 @@ __global__ __launch_bounds__(1024) void k_conserve(double *Q, double *mom, const
     q[h] = v;
   };
   if constexpr (PPT > 0) {
+    // The lane index goes through an empty asm statement, so that the
+    // coordinates are rebuilt here instead of being held in registers from
+    // the first pass (64 more live doubles at PPT = 16: they spilled).
+    int lane = threadIdx.x;
+    asm volatile("" : "+v"(lane));
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
-      const long h = threadIdx.x + long(i) * blockDim.x;
+      const long h = lane + long(i) * blockDim.x;
       if (h < nh) fix(h, keep[i]);
     }
   } else {
