@@ -1054,8 +1054,10 @@ struct Engine {
 // bit-identical.  NC > 0 fixes N at compile time, so that rebuilding a point's
 // indices takes shifts and multiplications instead of integer divisions by a
 // runtime value (which dominated the kernel's instruction count).
+constexpr int kConserveBlock = 1024;   // lanes per workgroup of k_conserve
+
 template <int PPT, int NC = 0>
-__global__ __launch_bounds__(1024) void k_conserve(double *Q, double *mom, const double *ginv, int Nrt, double L,
+__global__ __launch_bounds__(kConserveBlock) void k_conserve(double *Q, double *mom, const double *ginv, int Nrt, double L,
                                                    int *flag, double dc3, const double *isc, int K) {
   const int N = NC > 0 ? NC : Nrt;
   const long n3 = long(N) * N * N;
@@ -1085,13 +1087,18 @@ __global__ __launch_bounds__(1024) void k_conserve(double *Q, double *mom, const
   };
   double2 keep[PPT > 0 ? PPT : 1];
   if constexpr (PPT > 0) {
+    // every load is issued before the first sum: the index is clamped instead
+    // of guarded (a guarded load sits in a branch of its own, and the compiler
+    // then waits for each load before the next one is issued)
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
-      const long h = threadIdx.x + long(i) * blockDim.x;
-      if (h < nh) {
-        keep[i] = q[h];
-        add(h, keep[i]);
-      }
+      const long h = threadIdx.x + long(i) * kConserveBlock;
+      keep[i] = q[h < nh ? h : nh - 1];
+    }
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const long h = threadIdx.x + long(i) * kConserveBlock;
+      if (h < nh) add(h, keep[i]);
     }
   } else {
     for (long h = threadIdx.x; h < nh; h += blockDim.x) add(h, q[h]);
@@ -1137,7 +1144,7 @@ __global__ __launch_bounds__(1024) void k_conserve(double *Q, double *mom, const
     asm volatile("" : "+v"(lane));
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
-      const long h = lane + long(i) * blockDim.x;
+      const long h = lane + long(i) * kConserveBlock;
       if (h < nh) fix(h, keep[i]);
     }
   } else {
@@ -1345,7 +1352,7 @@ qcoll_status launch_conserve(const Plan &p, int64_t batch, double *Q, double *mo
   TimedLaunch tl("conserve", st);
   // pairs per lane of the register-resident variant: N^3 / 2 / 1024, rounded up
   auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3(unsigned(batch)), dim3(1024), 0, st, Q, mom, p.ginv, p.N, p.L, p.flag,
+    hipLaunchKernelGGL(kern, dim3(unsigned(batch)), dim3(kConserveBlock), 0, st, Q, mom, p.ginv, p.N, p.L, p.flag,
                        dc * dc * dc, isc, K);
   };
   switch (p.N) {
