@@ -390,6 +390,54 @@ struct SrcLossHalf {
 // and of the loss spectrum (FP64), then Q = Re(gain) - f * Re(loss) in FP64.
 // With isc set, item b0 + b of the call is scaled by isc[(b0 + b) % K] (the
 // collocation weights of the DG weak form, folded into this store).
+// Second half of the assembly along one axis-1 pencil: Q = sc * (gain - f *
+// ifft(L)) with gain the pencil's transformed gain spectrum, L the loss
+// spectrum (all N planes, or with HALF the planes k1 <= N/2 of a Hermitian
+// spectrum, completed in registers).  Up to N = 32 the gain values stay in
+// registers; from N = 48 on (a pencil of N complex doubles is then 192 and more
+// registers) they go to Q first and are read back by the same lane after the
+// loss transform, which keeps one pencil live at a time instead of spilling.
+template <int N, bool HALF = false>
+__device__ __forceinline__ void assemble_loss(double (&out)[N], const C<double> *x1, const double *fb, double *qb,
+                                              double sc) {
+  constexpr long n2 = long(N) * N;
+  constexpr int H1 = N / 2 + 1;
+  constexpr bool SPLIT = N >= 48;
+  if constexpr (SPLIT) static_for<0, N>([&](auto j) { qb[decltype(j)::value * n2] = out[decltype(j)::value]; });
+  double lr[N], li[N];
+  static_for<0, HALF ? H1 : N>([&](auto k) {
+    const C<double> l = x1[decltype(k)::value * n2];
+    lr[decltype(k)::value] = l.re;
+    li[decltype(k)::value] = l.im;
+  });
+  if constexpr (HALF) {
+    static_for<H1, N>([&](auto k) {
+      lr[decltype(k)::value] = lr[N - decltype(k)::value];
+      li[decltype(k)::value] = -li[N - decltype(k)::value];
+    });
+  }
+  fft_reg<N, +1, double>(lr, li);
+  // groups of G points: the group's loads of f (and of the stored gain) are
+  // issued before its stores (Q may alias f as far as the compiler knows, so
+  // a load after a store would wait for it)
+  constexpr int G = (N % 8 == 0) ? 8 : 4;
+  static_for<0, N / G>([&](auto gg) {
+    constexpr int j0 = decltype(gg)::value * G;
+    double fv[G], gv[G];
+    static_for<0, G>([&](auto i) {
+      constexpr int jj = j0 + decltype(i)::value;
+      fv[decltype(i)::value] = fb[jj * n2];
+      gv[decltype(i)::value] = SPLIT ? qb[jj * n2] : out[jj];
+    });
+    static_for<0, G>([&](auto i) {
+      constexpr int jj = j0 + decltype(i)::value;
+      double o = gv[decltype(i)::value];
+      o -= fv[decltype(i)::value] * lr[jj];
+      qb[jj * n2] = sc * o;
+    });
+  });
+}
+
 template <typename T, int N>
 struct OpAssemble {
   const C<T> *TA;
@@ -413,24 +461,7 @@ struct OpAssemble {
       fft_reg<N, +1, T>(ar, ai);
       static_for<0, N>([&](auto j) { out[decltype(j)::value] = double(ar[decltype(j)::value]); });
     }
-    {
-      double lr[N], li[N];
-      const C<double> *x1 = LH + b * n3 + r;
-      static_for<0, N>([&](auto k) {
-        const C<double> l = x1[decltype(k)::value * n2];
-        lr[decltype(k)::value] = l.re;
-        li[decltype(k)::value] = l.im;
-      });
-      fft_reg<N, +1, double>(lr, li);
-      const double *fb = f + b * n3 + r;
-      static_for<0, N>([&](auto j) {
-        constexpr int jj = decltype(j)::value;
-        out[jj] -= fb[jj * n2] * lr[jj];
-      });
-    }
-    const double sc = isc ? isc[(b0 + b) % K] : 1.0;
-    double *qb = Q + b * n3 + r;
-    static_for<0, N>([&](auto j) { qb[decltype(j)::value * n2] = sc * out[decltype(j)::value]; });
+    assemble_loss<N>(out, LH + b * n3 + r, f + b * n3 + r, Q + b * n3 + r, isc ? isc[(b0 + b) % K] : 1.0);
   }
 };
 
@@ -465,28 +496,7 @@ struct OpAssembleHalf {
       fft_reg<N, +1, T>(ar, ai);
       static_for<0, N>([&](auto j) { out[decltype(j)::value] = double(ar[decltype(j)::value]); });
     }
-    {
-      double lr[N], li[N];
-      const C<double> *x1 = LH + b * n3 + r;
-      static_for<0, H1>([&](auto k) {
-        const C<double> l = x1[decltype(k)::value * n2];
-        lr[decltype(k)::value] = l.re;
-        li[decltype(k)::value] = l.im;
-      });
-      static_for<H1, N>([&](auto k) {
-        lr[decltype(k)::value] = lr[N - decltype(k)::value];
-        li[decltype(k)::value] = -li[N - decltype(k)::value];
-      });
-      fft_reg<N, +1, double>(lr, li);
-      const double *fb = f + b * n3 + r;
-      static_for<0, N>([&](auto j) {
-        constexpr int jj = decltype(j)::value;
-        out[jj] -= fb[jj * n2] * lr[jj];
-      });
-    }
-    const double sc = isc ? isc[(b0 + b) % K] : 1.0;
-    double *qb = Q + b * n3 + r;
-    static_for<0, N>([&](auto j) { qb[decltype(j)::value * n2] = sc * out[decltype(j)::value]; });
+    assemble_loss<N, true>(out, LH + b * n3 + r, f + b * n3 + r, Q + b * n3 + r, isc ? isc[(b0 + b) % K] : 1.0);
   }
 };
 
