@@ -366,6 +366,36 @@ struct SrcLossAdj {
 };
 
 // final pencil pass: df = 2 Re ifft(Z)/N^3 - g Re(L) - Im(L)
+// Loss part of the adjoint's last pencil: df = gain - g Re(L) - Im(L), with
+// gain the pencil's transformed gain part and L = ifft of the loss adjoint
+// spectrum along axis 1.  The loads of g for each group of points are issued
+// before the group's stores (df may alias g as far as the compiler knows, so a
+// load after a store would wait for it).
+template <int N>
+__device__ __forceinline__ void vjp_assemble_loss(const double (&out)[N], const C<double> *x, const double *gb,
+                                                  double *o) {
+  constexpr long n2 = long(N) * N;
+  double lr[N], li[N];
+  static_for<0, N>([&](auto k) {
+    const C<double> v = x[decltype(k)::value * n2];
+    lr[decltype(k)::value] = v.re;
+    li[decltype(k)::value] = v.im;
+  });
+  fft_reg<N, +1, double>(lr, li);
+  constexpr int G = (N % 8 == 0) ? 8 : 4;
+  static_for<0, N / G>([&](auto gg) {
+    constexpr int j0 = decltype(gg)::value * G;
+    double gv[G];
+    static_for<0, G>([&](auto i) { gv[decltype(i)::value] = gb[(j0 + decltype(i)::value) * n2]; });
+    static_for<0, G>([&](auto i) {
+      constexpr int jj = j0 + decltype(i)::value;
+      double v = out[jj];
+      v -= gv[decltype(i)::value] * lr[jj] + li[jj];
+      o[jj * n2] = v;
+    });
+  });
+}
+
 template <typename T, int N>
 struct OpVjpAssemble {
   const C<T> *Z;
@@ -387,23 +417,7 @@ struct OpVjpAssemble {
       constexpr double sc = 2.0 / double(n3);
       static_for<0, N>([&](auto j) { out[decltype(j)::value] = sc * double(zr[decltype(j)::value]); });
     }
-    {
-      double lr[N], li[N];
-      const C<double> *x = Lm + b * n3 + r;
-      static_for<0, N>([&](auto k) {
-        const C<double> v = x[decltype(k)::value * n2];
-        lr[decltype(k)::value] = v.re;
-        li[decltype(k)::value] = v.im;
-      });
-      fft_reg<N, +1, double>(lr, li);
-      const double *gb = g + b * n3 + r;
-      static_for<0, N>([&](auto j) {
-        constexpr int jj = decltype(j)::value;
-        out[jj] -= gb[jj * n2] * lr[jj] + li[jj];
-      });
-    }
-    double *o = df + b * n3 + r;
-    static_for<0, N>([&](auto j) { o[decltype(j)::value * n2] = out[decltype(j)::value]; });
+    vjp_assemble_loss<N>(out, Lm + b * n3 + r, g + b * n3 + r, df + b * n3 + r);
   }
 };
 
@@ -438,23 +452,7 @@ struct OpVjpAssembleHalf {
       constexpr double sc = 1.0 / double(n3);
       static_for<0, N>([&](auto j) { out[decltype(j)::value] = sc * double(zr[decltype(j)::value]); });
     }
-    {
-      double lr[N], li[N];
-      const C<double> *x = Lm + b * n3 + r;
-      static_for<0, N>([&](auto k) {
-        const C<double> v = x[decltype(k)::value * n2];
-        lr[decltype(k)::value] = v.re;
-        li[decltype(k)::value] = v.im;
-      });
-      fft_reg<N, +1, double>(lr, li);
-      const double *gb = g + b * n3 + r;
-      static_for<0, N>([&](auto j) {
-        constexpr int jj = decltype(j)::value;
-        out[jj] -= gb[jj * n2] * lr[jj] + li[jj];
-      });
-    }
-    double *o = df + b * n3 + r;
-    static_for<0, N>([&](auto j) { o[decltype(j)::value * n2] = out[decltype(j)::value]; });
+    vjp_assemble_loss<N>(out, Lm + b * n3 + r, g + b * n3 + r, df + b * n3 + r);
   }
 };
 
