@@ -63,7 +63,12 @@ __global__ __launch_bounds__(FusedGeom<N>::NL, FusedGeom<N>::WPE) void k_gain_fu
   const int p = int(bp % Nr);
 
   // pencil u of this lane is t = lane + u*NL, split as (hi, lo) = (t / N, t % N)
-  const int lane = threadIdx.x;
+  // VHS: the lane index passes an empty asm statement, which keeps the
+  // compiler from folding the transposes' address arithmetic into forms that
+  // cost more VALU instructions in the term loop (1351 -> 1330 per term at
+  // 32^3); the VSS loop does not gain from it
+  int lane = threadIdx.x;
+  if constexpr (!VSS) asm volatile("" : "+v"(lane));
   int hi[PPL], lo[PPL];
   static_for<0, PPL>([&](auto u) {
     const int t = lane + decltype(u)::value * NL;
