@@ -236,6 +236,14 @@ __global__ __launch_bounds__(FusedGeom<N>::NL, FusedGeom<N>::WPE) void k_gain_fu
   // their truncation, already / N^3), stored as the spectrum W[item][p].
   // lane (j1, j2): axis 3; lane (j1, k3): axis 2; lane (k2, k3): axis 1.
   {
+    // the lane coordinates again from the thread index, so that none of the
+    // term loop's values has to be kept across it for this stage
+    lane = threadIdx.x;
+    static_for<0, PPL>([&](auto u) {
+      const int t = lane + decltype(u)::value * NL;
+      hi[decltype(u)::value] = t / N;
+      lo[decltype(u)::value] = t % N;
+    });
     if constexpr (G::WAVE_BC) __syncthreads();
     float zr[PPL][N], zi[PPL][N];
     static_for<0, PPL>([&](auto uu) {
